@@ -1,0 +1,435 @@
+"""Pins of the CPU oracle against things other than itself: a library
+generator, the paper's printed block counts, closed forms, invariants and a
+pure-Python brute force with exact rational arithmetic (tests/brute.py)."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import brute
+from synth import fbm, uniform_observers
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _rand_terrain(rng, nr, nc, lo=0, hi=40):
+    return rng.integers(lo, hi + 1, size=(nr, nc)).astype(np.int16)
+
+
+# ---------------------------------------------------------------- RNG ------
+def _dec256(ctr):
+    # counter - 1 over the 256-bit little-endian word vector (wraps at 0)
+    v = sum(int(w) << (64 * i) for i, w in enumerate(ctr))
+    v = (v - 1) % (1 << 256)
+    return [(v >> (64 * i)) & (2**64 - 1) for i in range(4)]
+
+
+@pytest.mark.parametrize("ctr,key", [
+    ([0, 0, 0, 0], [0, 0]),
+    ([1, 2, 3, 4], [5, 6]),
+    ([2**64 - 1] * 4, [2**64 - 1] * 2),
+    ([123456789, 7, 0, 0], [0xdeadbeef, 0]),
+])
+def test_philox_matches_numpy(orc, ctr, key):
+    # numpy's Philox (4x64-10) increments its counter before each block, so a
+    # counter preset to c-1 yields block(c).
+    c = np.array(ctr, dtype=object)
+    prev = _dec256(ctr)
+    bg = np.random.Philox(key=np.array(key, dtype=np.uint64),
+                          counter=np.array(prev, dtype=np.uint64))
+    want = bg.random_raw(4)
+    got = orc.philox4x64_10(np.array([int(v) for v in c], dtype=np.uint64), key)
+    assert [int(v) for v in got] == [int(v) for v in want]
+
+
+# ---------------------------------------------------------------- LOS ------
+def test_los_brute_force_all_pairs(orc):
+    rng = np.random.default_rng(11)
+    for trial in range(6):
+        nr, nc = int(rng.integers(5, 11)), int(rng.integers(5, 11))
+        z = _rand_terrain(rng, nr, nc, 0, 30)
+        zl = z.tolist()
+        h_t, h_r = int(rng.integers(0, 6)), int(rng.integers(0, 6))
+        for ty in range(nr):
+            for tx in range(nc):
+                for py in range(nr):
+                    for px in range(nc):
+                        a = orc.los(z, (tx, ty), (px, py), h_t, h_r)
+                        b = brute.los(zl, (tx, ty), (px, py), h_t, h_r)
+                        assert a == b, (trial, tx, ty, px, py)
+
+
+def test_los_flat_and_symmetry(orc):
+    z = np.full((9, 12), 7, np.int16)
+    for p in [(0, 0), (11, 8), (5, 0), (11, 3)]:
+        assert orc.los(z, (4, 4), p, 0, 0)
+    rng = np.random.default_rng(3)
+    z = _rand_terrain(rng, 12, 12, 0, 50)
+    for _ in range(300):
+        t = tuple(int(v) for v in rng.integers(0, 12, 2))
+        p = tuple(int(v) for v in rng.integers(0, 12, 2))
+        h = int(rng.integers(0, 10))
+        # the same segment and grid-line crossings in both directions
+        assert orc.los(z, t, p, h, h) == orc.los(z, p, t, h, h)
+
+
+def test_los_single_wall_closed_form(orc):
+    # flat z=0, a wall of height W in column tx+a; receiver in row ty at dx>a:
+    # visible iff the segment at the wall, h_t + (h_r-h_t)*a/dx, is >= W.
+    nr, nc, tx, ty = 5, 40, 2, 2
+    for W in (3, 10, 25):
+        for a in (1, 3, 7):
+            z = np.zeros((nr, nc), np.int16)
+            z[:, tx + a] = W
+            for h_t, h_r in [(5, 1), (20, 2), (30, 30), (1, 40)]:
+                for dx in range(a + 1, nc - tx):
+                    want = h_t * dx + (h_r - h_t) * a >= W * dx
+                    assert orc.los(z, (tx, ty), (tx + dx, ty), h_t, h_r) == want
+
+
+def test_los_monotone_in_heights(orc):
+    rng = np.random.default_rng(5)
+    z = _rand_terrain(rng, 16, 16, 0, 60)
+    for _ in range(400):
+        t = tuple(int(v) for v in rng.integers(0, 16, 2))
+        p = tuple(int(v) for v in rng.integers(0, 16, 2))
+        h1, h2 = sorted(int(v) for v in rng.integers(0, 30, 2))
+        assert orc.los(z, t, p, h1, 5) <= orc.los(z, t, p, h2, 5)
+        assert orc.los(z, t, p, 5, h1) <= orc.los(z, t, p, 5, h2)
+
+
+# ---------------------------------------------------------------- VIX ------
+def test_vix_targets_valid_and_counted(orc):
+    rng = np.random.default_rng(8)
+    z = _rand_terrain(rng, 20, 17, 0, 40)
+    R, K, seed = 6, 12, 99
+    cnt = orc.vix(z, R, 3, 2, K, seed)
+    zl = z.tolist()
+    for y in range(20):
+        for x in range(17):
+            tx, ty = orc.vix_targets(20, 17, x, y, R, K, seed)
+            c = 0
+            for px, py in zip(tx.tolist(), ty.tolist()):
+                assert px >= 0
+                assert (px, py) != (x, y)
+                assert (px - x) ** 2 + (py - y) ** 2 <= R * R
+                assert 0 <= px < 17 and 0 <= py < 20
+                c += brute.los(zl, (x, y), (px, py), 3, 2)
+            assert c == cnt[y, x]
+
+
+def test_vix_draw_formula_from_numpy_philox(orc):
+    # the first accepted attempt of draw j is word (a mod 4) of the Philox
+    # block {t, j, a//4, 0} keyed {seed, 0}, mapped into the clipped box.
+    nr, nc, R, seed = 50, 60, 7, 1234
+    for (x, y) in [(0, 0), (30, 20), (59, 49), (3, 45)]:
+        tx, ty = orc.vix_targets(nr, nc, x, y, R, 5, seed)
+        t = y * nc + x
+        bx0, bx1 = max(0, x - R), min(nc - 1, x + R)
+        by0, by1 = max(0, y - R), min(nr - 1, y + R)
+        for j in range(5):
+            a = 0
+            while True:
+                if a % 4 == 0:
+                    prev = _dec256([t, j, a // 4, 0])
+                    blk = np.random.Philox(key=np.array([seed, 0], np.uint64),
+                                           counter=np.array(prev, np.uint64)).random_raw(4)
+                u = int(blk[a % 4])
+                px = bx0 + (((u >> 32) * (bx1 - bx0 + 1)) >> 32)
+                py = by0 + (((u & 0xffffffff) * (by1 - by0 + 1)) >> 32)
+                if (px, py) != (x, y) and (px - x) ** 2 + (py - y) ** 2 <= R * R:
+                    break
+                a += 1
+            assert (tx[j], ty[j]) == (px, py)
+
+
+def test_vix_flat_is_full_and_monotone(orc):
+    z = np.full((30, 30), 100, np.int16)
+    assert (orc.vix(z, 8, 0, 0, 10, 1) == 10).all()
+    z = fbm(48, 2.4, 300, 2)
+    a = orc.vix(z, 10, 2, 2, 16, 5).astype(int)
+    b = orc.vix(z, 10, 20, 2, 16, 5).astype(int)
+    c = orc.vix(z, 10, 20, 30, 16, 5).astype(int)
+    assert (a <= b).all() and (b <= c).all()
+
+
+def test_vix_targets_uniform_chi2(orc):
+    # draws of one interior post over many seeds: chi-square over disk cells
+    R, nr, nc, x, y = 4, 20, 20, 10, 10
+    cells = sorted((dx, dy) for dx in range(-R, R + 1) for dy in range(-R, R + 1)
+                   if (dx, dy) != (0, 0) and dx * dx + dy * dy <= R * R)
+    idx = {c: i for i, c in enumerate(cells)}
+    counts = np.zeros(len(cells))
+    for seed in range(200):
+        tx, ty = orc.vix_targets(nr, nc, x, y, R, 40, seed)
+        for px, py in zip(tx.tolist(), ty.tolist()):
+            counts[idx[(px - x, py - y)]] += 1
+    e = counts.sum() / len(cells)
+    chi2 = float(((counts - e) ** 2 / e).sum())
+    dof = len(cells) - 1
+    # mean dof, sd sqrt(2 dof): 5 sigma bound
+    assert chi2 < dof + 5 * math.sqrt(2 * dof)
+
+
+def test_vix_clipped_corner_draws(orc):
+    tx, ty = orc.vix_targets(3, 3, 0, 0, 50, 100, 7)
+    for px, py in zip(tx.tolist(), ty.tolist()):
+        assert 0 <= px < 3 and 0 <= py < 3 and (px, py) != (0, 0)
+    seen = set(zip(tx.tolist(), ty.tolist()))
+    assert seen == {(a, b) for a in range(3) for b in range(3)} - {(0, 0)}
+
+
+# ------------------------------------------------------------ FINDMAX ------
+def test_block_grid_matches_paper_tables(orc):
+    rows = [l.split() for l in open(os.path.join(HERE, "golden", "paper_blocks.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) == 5
+    for n, roi, g, k, m in [[int(v) for v in r] for r in rows]:
+        assert orc.block_grid(n, roi) == g
+        assert g * g * k == m
+
+
+def _findmax_numpy(key, z, gr, gc, k):
+    nr, nc = z.shape
+    out = []
+    for bi in range(gr):
+        for bj in range(gc):
+            r0, r1 = bi * nr // gr, (bi + 1) * nr // gr
+            c0, c1 = bj * nc // gc, (bj + 1) * nc // gc
+            yy, xx = np.mgrid[r0:r1, c0:c1]
+            idx = (yy * nc + xx).ravel()
+            kk = key[r0:r1, c0:c1].ravel().astype(np.int64)
+            zz = z[r0:r1, c0:c1].ravel().astype(np.int64)
+            order = np.lexsort((idx, -zz, -kk))
+            top = idx[order][:k].tolist()
+            out += top + [-1] * (k - len(top))
+    return np.array(out, np.int64)
+
+
+@pytest.mark.parametrize("shape,gr,gc,k", [((37, 41), 3, 4, 5), ((20, 20), 5, 5, 20),
+                                           ((64, 30), 7, 2, 3), ((9, 9), 9, 9, 2)])
+def test_findmax_lexsort(orc, shape, gr, gc, k):
+    rng = np.random.default_rng(shape[0] * 7 + k)
+    key = rng.integers(0, 4, size=shape).astype(np.uint8)   # many ties
+    z = rng.integers(0, 5, size=shape).astype(np.int16)
+    assert (orc.findmax(key, z, gr, gc, k) == _findmax_numpy(key, z, gr, gc, k)).all()
+
+
+def test_findmax_f32_strided(orc):
+    rng = np.random.default_rng(4)
+    z = rng.integers(0, 9, size=(23, 29)).astype(np.int16)
+    s = 3
+    kr, kc = -(-23 // s), -(-29 // s)
+    sc = rng.integers(0, 5, size=(kr, kc)).astype(np.float32)
+    sc[1, 2] = np.nan
+    got = orc.findmax(sc, z, 2, 3, 4, stride=s)
+    for b in range(6):
+        bi, bj = divmod(b, 3)
+        r0, r1 = bi * 23 // 2, (bi + 1) * 23 // 2
+        c0, c1 = bj * 29 // 3, (bj + 1) * 29 // 3
+        items = []
+        for y in range(r0, r1):
+            for x in range(c0, c1):
+                if y % s == 0 and x % s == 0:
+                    v = float(sc[y // s, x // s])
+                    items.append((-(v if v == v else -np.inf), y * 29 + x))
+        items.sort()
+        want = [i for _, i in items[:4]] + [-1] * max(0, 4 - len(items))
+        assert got[b * 4:(b + 1) * 4].tolist() == want
+
+
+# ----------------------------------------------------------- VIEWSHED ------
+def _obs(orc, x, y, R, ht, hr):
+    return orc.observers([x], [y], [R], [ht], [hr])
+
+
+def test_viewshed_brute_force_tiny(orc):
+    rng = np.random.default_rng(21)
+    for trial in range(40):
+        nr, nc = int(rng.integers(4, 26)), int(rng.integers(4, 26))
+        z = _rand_terrain(rng, nr, nc, 0, int(rng.integers(1, 60)))
+        x, y = int(rng.integers(0, nc)), int(rng.integers(0, nr))
+        R = int(rng.integers(1, 14))
+        ht, hr = int(rng.integers(0, 12)), int(rng.integers(0, 12))
+        ob = _obs(orc, x, y, R, ht, hr)
+        got = brute.bitmap_to_set(orc.viewshed_one(z, ob), nr, nc, (x, y, R))
+        want = brute.viewshed(z.tolist(), (x, y, R, ht, hr))
+        assert got == want, trial
+
+
+def test_viewshed_flat_is_disk(orc):
+    for (nr, nc, x, y, R) in [(40, 40, 20, 20, 13), (30, 70, 0, 5, 9), (25, 25, 24, 24, 30),
+                              (130, 150, 64, 70, 60)]:
+        z = np.full((nr, nc), 55, np.int16)
+        ob = _obs(orc, x, y, R, 0, 0)
+        got = brute.bitmap_to_set(orc.viewshed_one(z, ob), nr, nc, (x, y, R))
+        assert got == brute.disk(nr, nc, x, y, R)
+
+
+def test_viewshed_every_disk_cell_visited(orc):
+    # with an enormous receiver height every visited cell is visible, so the
+    # bitmap is exactly the set of cells some ray reaches: the whole disk.
+    z = fbm(160, 2.2, 900, 3)
+    for (x, y, R) in [(80, 80, 70), (0, 80, 45), (159, 3, 100), (40, 120, 1), (90, 60, 2)]:
+        ob = _obs(orc, x, y, R, 0, 30000)
+        got = brute.bitmap_to_set(orc.viewshed_one(z, ob), 160, 160, (x, y, R))
+        assert got == brute.disk(160, 160, x, y, R)
+
+
+def test_viewshed_single_wall(orc):
+    nr, nc, tx, ty, R = 61, 61, 30, 30, 28
+    for W, a, ht, hr in [(40, 4, 10, 5), (12, 9, 10, 10), (100, 2, 50, 1)]:
+        z = np.zeros((nr, nc), np.int16)
+        z[:, tx + a] = W
+        ob = _obs(orc, tx, ty, R, ht, hr)
+        vis = brute.bitmap_to_set(orc.viewshed_one(z, ob), nr, nc, (tx, ty, R))
+        for dy in range(-R, R + 1):
+            for dx in range(1, R + 1):
+                if dx * dx + dy * dy > R * R or abs(dy) >= dx:
+                    continue
+                cell = (tx + dx, ty + dy)
+                if dx < a:
+                    assert cell in vis
+                elif dx > a:
+                    assert (cell in vis) == ((hr - ht) * a >= (W - ht) * dx), (W, a, cell)
+
+
+def test_viewshed_one_side_clipped_equals_los(orc):
+    # observer d columns from the right edge: cells (d, m) with |m| < d are
+    # marked only by their own ray, at a step where the ray passes exactly
+    # through them, so the bitmap equals per-cell line of sight there.
+    z = fbm(120, 2.4, 600, 9)
+    for d, R, ht, hr in [(12, 30, 5, 2), (25, 40, 1, 1), (7, 7, 10, 0)]:
+        x, y = 119 - d, 60
+        ob = _obs(orc, x, y, R, ht, hr)
+        vis = brute.bitmap_to_set(orc.viewshed_one(z, ob), 120, 120, (x, y, R))
+        for m in range(-d + 1, d):
+            if d * d + m * m > R * R:
+                continue
+            cell = (x + d, y + m)
+            assert (cell in vis) == orc.los(z, (x, y), cell, ht, hr)
+
+
+def test_viewshed_ray_steps_through_cells_equal_los(orc):
+    # brute per-ray dump: at a step with no fractional offset the ray's
+    # verdict is per-cell line of sight to that cell (the horizon is the
+    # maximum slope of exactly the samples that LOS tests).
+    z = fbm(64, 2.2, 400, 4)
+    zl = z.tolist()
+    x, y, R, ht, hr = 30, 33, 25, 6, 3
+    x0, x1, y0, y1 = brute.window(64, 64, x, y, R)
+    for by in range(y0, y1 + 1):
+        for bx in range(x0, x1 + 1):
+            if not (bx in (x0, x1) or by in (y0, y1)):
+                continue
+            dump = []
+            brute.ray(zl, 64, 64, (x, y, R, ht, hr), bx, by, dump)
+            for k, frac, cell, vis in dump:
+                if frac == 0:
+                    assert vis == brute.los(zl, (x, y), cell, ht, hr)
+
+
+def test_viewshed_monotone_ring_and_d4(orc):
+    z = fbm(90, 2.4, 700, 12)
+    x, y, R = 40, 47, 30
+    sets = {}
+    for ht, hr in [(2, 2), (10, 2), (10, 9)]:
+        ob = _obs(orc, x, y, R, ht, hr)
+        sets[(ht, hr)] = brute.bitmap_to_set(orc.viewshed_one(z, ob), 90, 90, (x, y, R))
+    assert sets[(2, 2)] <= sets[(10, 2)] <= sets[(10, 9)]
+    ring = {(x + a, y + b) for a in (-1, 0, 1) for b in (-1, 0, 1)}
+    assert ring <= sets[(2, 2)]
+    base = sets[(10, 2)]
+    # the 8 symmetries of the square, applied to terrain and observer
+    for tr in range(8):
+        zt = z.T if tr & 4 else z
+        px, py = (y, x) if tr & 4 else (x, y)
+        if tr & 1:
+            zt = zt[:, ::-1]; px = 89 - px
+        if tr & 2:
+            zt = zt[::-1, :]; py = 89 - py
+        zt = np.ascontiguousarray(zt)
+        ob = _obs(orc, px, py, R, 10, 2)
+        got = brute.bitmap_to_set(orc.viewshed_one(zt, ob), 90, 90, (px, py, R))
+
+        def fwd(c):
+            cx, cy = (c[1], c[0]) if tr & 4 else c
+            if tr & 1:
+                cx = 89 - cx
+            if tr & 2:
+                cy = 89 - cy
+            return (cx, cy)
+        assert got == {fwd(c) for c in base}, tr
+
+
+def test_viewshed_batch_layout_and_count(orc):
+    z = fbm(100, 2.4, 500, 6)
+    obs = uniform_observers(100, 100, 25, 3, roi=(3, 40), height=(0, 20))
+    bm, off = orc.viewshed(z, obs)
+    vis, cells = orc.viewshed_count(z, obs)
+    for i, o in enumerate(obs):
+        one = orc.viewshed_one(z, o)
+        assert (bm[off[i]:off[i + 1]] == one.ravel()).all()
+        assert vis[i] == sum(bin(int(v)).count("1") for v in one.ravel())
+        assert cells[i] == len(brute.disk(100, 100, int(o["x"]), int(o["y"]), int(o["roi"])))
+
+
+# --------------------------------------------------------------- SITE ------
+def _sets_from(orc, z, obs):
+    nr, nc = z.shape
+    bm, off = orc.viewshed(z, obs)
+    sets = []
+    for i, o in enumerate(obs):
+        w = bm[off[i]:off[i + 1]]
+        R = int(o["roi"])
+        x0 = max(0, int(o["x"]) - R)
+        nw = ((min(nc - 1, int(o["x"]) + R)) >> 6) - (x0 >> 6) + 1
+        sets.append(brute.bitmap_to_set(w.reshape(-1, nw), nr, nc,
+                                        (int(o["x"]), int(o["y"]), R)))
+    return bm, off, sets
+
+
+def test_greedy_brute_lazy_and_invariants(orc):
+    for seed in range(4):
+        z = fbm(80, 2.4, 400, 30 + seed)
+        obs = uniform_observers(80, 80, 30, seed, roi=(4, 25), height=(1, 15))
+        bm, off, sets = _sets_from(orc, z, obs)
+        target = int(math.ceil(0.9 * 80 * 80))
+        sel, gains, cum = orc.greedy(bm, off, obs, 80, 80, 20, target)
+        bsel, bgains, bcov = brute.greedy_sets(sets, 20, target)
+        assert sel.tolist() == bsel and gains.tolist() == bgains
+        lsel, lgains, lcum, evals = orc.greedy(bm, off, obs, 80, 80, 20, target, lazy=True)
+        assert lsel.tolist() == sel.tolist() and lgains.tolist() == gains.tolist()
+        assert (lcum == cum).all()
+        # gains never grow (submodularity); sum of gains is the union's area
+        assert all(gains[i] >= gains[i + 1] for i in range(len(gains) - 1))
+        pop = sum(bin(int(v)).count("1") for v in cum.ravel())
+        assert pop == int(gains.sum()) == len(bcov)
+
+
+def test_greedy_stop_rules(orc):
+    z = fbm(64, 2.4, 300, 1)
+    obs = uniform_observers(64, 64, 12, 2, roi=(5, 30), height=(2, 10))
+    bm, off, sets = _sets_from(orc, z, obs)
+    sel, gains, _ = orc.greedy(bm, off, obs, 64, 64, 5, 10**9)
+    assert len(sel) == 5
+    sel, gains, _ = orc.greedy(bm, off, obs, 64, 64, 100, 10**9)
+    # stops at zero gain: every candidate's cells are covered
+    u = set().union(*sets)
+    assert int(gains.sum()) == len(u) and len(sel) <= 12
+    tgt = int(gains[0]) + 1
+    sel2, gains2, _ = orc.greedy(bm, off, obs, 64, 64, 100, tgt)
+    assert len(sel2) == 2
+
+
+def test_greedy_approximation_bound(orc):
+    # greedy >= (1 - 1/e) of the exhaustive optimum (Nemhauser-Wolsey-Fisher)
+    for seed in range(3):
+        z = fbm(48, 2.4, 300, 50 + seed)
+        obs = uniform_observers(48, 48, 10, 70 + seed, roi=(4, 16), height=(1, 6))
+        bm, off, sets = _sets_from(orc, z, obs)
+        for m in (2, 3):
+            sel, gains, _ = orc.greedy(bm, off, obs, 48, 48, m, 10**9)
+            opt = brute.best_cover(sets, m)
+            assert int(gains.sum()) >= (1 - 1 / math.e) * opt
