@@ -1,0 +1,228 @@
+/*
+ * siting.h -- C ABI of libsiting.so, the MI355X (gfx950) implementation of the
+ * multiple-observer siting pipeline of Franklin, Magalhaes and Li, "Siting
+ * thousands of radio transmitter towers on terrains with billions of points"
+ * (arXiv 2006.16783), section "The multiple transmitter siting process":
+ *
+ *     VIX -> FINDMAX -> VIEWSHED -> SITE
+ *
+ * plus the learned ranking (a small CNN whose score can replace VIX as the
+ * FINDMAX key).
+ *
+ * Conventions (every entry point):
+ *  - Pointers are DEVICE pointers unless the parameter name ends in _host.
+ *    The caller owns every buffer; the library never allocates device memory.
+ *    Scratch memory is passed in as a workspace whose size a *_workspace_size
+ *    query returns.
+ *  - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL = the
+ *    default stream).  Outputs are valid once the stream has synchronised.
+ *  - Return value: SITING_OK (0) or a negative SITING_E_* code.  Arguments are
+ *    validated on the host before anything is enqueued; on error nothing is
+ *    enqueued and siting_last_error() (thread-local) describes the problem.
+ *  - Terrain: int16 elevation posts, row-major, nrows x ncols, leading
+ *    dimension ld >= ncols (posts between row starts).  x is the column, y the
+ *    row, posts one unit apart (section "Terrain visibility").  All post
+ *    indices are int64 (y * ncols + x), since 46400^2 > 2^31.
+ *  - Heights h_t (transmitter) and h_r (receiver) are integers in z's unit,
+ *    0 <= h <= 32767; the ROI is an integer number of posts, 1 <= roi <= 16383.
+ *  - All integer results are deterministic and independent of the schedule.
+ */
+#ifndef SITING_H
+#define SITING_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SITING_ABI_VERSION 1
+
+enum {
+    SITING_OK = 0,
+    SITING_E_INVALID = -1,      /* bad argument (null pointer, range, shape) */
+    SITING_E_UNSUPPORTED = -2,  /* valid but beyond this build's limits */
+    SITING_E_HIP = -3,          /* a HIP runtime call failed */
+    SITING_E_WORKSPACE = -4,    /* workspace missing or too small */
+    SITING_E_INTERNAL = -5      /* internal invariant broken */
+};
+
+/* One observer (tentative transmitter) and its viewshed parameters
+ * (Definitions: transmitter, transmitter height, radius of interest,
+ * receiver height).  Plain 20-byte record, 4-byte aligned. */
+typedef struct {
+    int32_t x;    /* column of the transmitter base, 0 <= x < ncols */
+    int32_t y;    /* row, 0 <= y < nrows */
+    int32_t roi;  /* radius of interest in posts, 1..16383 */
+    int32_t h_t;  /* transmitter height above its base, 0..32767 */
+    int32_t h_r;  /* receiver height above the terrain, 0..32767 */
+} siting_observer;
+
+/* Launch schedule of siting_viewshed_batch (see that function). */
+typedef struct {
+    int32_t waves;          /* wavefronts (64 lanes) per workgroup: 1..16 */
+    int32_t groups_per_cu;  /* resident workgroups per compute unit: 1..16 */
+    int32_t stage_rmax;     /* observers with roi <= stage_rmax stage their
+                               terrain quadrant in LDS; larger ones read the
+                               terrain through the cache hierarchy. 0 = none */
+    int32_t reserved;       /* must be 0 */
+} siting_schedule;
+
+enum { SITING_KEY_U8 = 0, SITING_KEY_F32 = 1 };
+enum { SITING_SINK_BITMAP = 0, SITING_SINK_COUNT = 1 };
+
+int siting_abi_version(void);
+
+/* Description of the last error on the calling thread ("" if none). */
+const char *siting_last_error(void);
+
+/* Number of compute units of the current device (for sizing schedules). */
+int siting_device_cus(int32_t *cus_host);
+
+/* ---------------------------------------------------------------- VIX ----
+ * Estimated visibility index of every post (stage Vix): for each post T and
+ * each of K draws, a receiver P uniform over the lattice cells of T's ROI disk
+ * that lie inside the terrain (P != T), and the line-of-sight test between
+ * the eye z[T]+h_t and the receiver top z[P]+h_r.  The LOS samples the
+ * terrain where the segment crosses each grid line of its major axis,
+ * linearly interpolated between the two adjacent posts ("Terrain
+ * visibility"), and is blocked only if the terrain is strictly above the
+ * segment.
+ * Draw j of post t = y*ncols+x takes attempts a = 0..63; attempt a uses word
+ * a%4 of Philox4x64-10(counter {t, j, a/4, 0}, key {seed, 0}) as u and the
+ * candidate  px = bx0 + (((u>>32) * wx) >> 32),
+ *            py = by0 + (((u & 0xffffffff) * wy) >> 32)
+ * in the terrain-clipped box [bx0, bx0+wx) x [by0, by0+wy) around T; it is
+ * accepted iff P != T and |P-T|^2 <= roi^2.  A draw with no accepted attempt
+ * counts as not visible.
+ *   z      : terrain (device), nrows x ncols, leading dimension ld
+ *   nrows, ncols >= 2; K in 1..255
+ *   count  : out (device), nrows x ncols uint8, contiguous row-major: the
+ *            number of visible receivers of each post (0..K).  */
+int siting_vix(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
+               int32_t roi, int32_t h_t, int32_t h_r, int32_t K, uint64_t seed,
+               uint8_t *count, void *stream);
+
+/* ------------------------------------------------------------ FINDMAX ----
+ * Spatially spread candidates (stage Findmax): the terrain is split into a
+ * grid_r x grid_c grid of blocks, block (bi,bj) spanning rows
+ * [floor(bi*nrows/grid_r), floor((bi+1)*nrows/grid_r)) and likewise columns;
+ * each block keeps its k best posts.
+ *   key_type SITING_KEY_U8 : key is uint8[nrows*ncols] (a VIX count); rank by
+ *            (key desc, z desc, linear index asc); key_stride must be 1.
+ *   key_type SITING_KEY_F32: key is float[ceil(nrows/s) * ceil(ncols/s)],
+ *            s = key_stride >= 1, scoring post (i*s, j*s); only those posts
+ *            are eligible; rank by (key desc, linear index asc); NaN ranks as
+ *            -infinity.
+ *   cand   : out (device), int64[grid_r*grid_c*k]: blocks in row-major
+ *            order, each with k post indices best first, padded with -1.
+ *   1 <= grid_r <= nrows, 1 <= grid_c <= ncols, 1 <= k <= 32.
+ * The paper's own default is blocks of width ROI/3 and k = 20, i.e.
+ * grid = round(N / floor(ROI/3)) per side. */
+int siting_findmax(const void *key, int32_t key_type, int32_t key_stride,
+                   const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
+                   int32_t grid_r, int32_t grid_c, int32_t k, int64_t *cand,
+                   void *stream);
+
+/* ----------------------------------------------------------- VIEWSHED ----
+ * Window bitmaps (stage Viewshed; bitmaps in 64-bit words).  Observer i's
+ * window covers rows [max(0,y-R), min(nrows-1,y+R)] and the 64-bit words
+ * [max(0,x-R)>>6, min(ncols-1,x+R)>>6] of each row, stored row-major at
+ * bitmaps + offsets[i]; bit (c & 63) of word (c >> 6) is column c, exactly
+ * as in a full-terrain bitmap of ceil(ncols/64) words per row.  Bits outside
+ * the ROI disk, outside the terrain, or in padding are 0.
+ *
+ * Host-only.  Writes offsets_host[0..n] (offsets_host[n] = total words) and
+ * returns the total number of words, or a negative SITING_E_* code. */
+int64_t siting_viewshed_layout(const siting_observer *obs_host, int64_t n, int64_t nrows,
+                               int64_t ncols, int64_t *offsets_host);
+
+/* Host-only.  A processing order (permutation of 0..n-1) by decreasing
+ * cost (roi, then index), so that a persistent launch takes the longest
+ * observers first.  Returns SITING_OK or an error code. */
+int siting_viewshed_order(const siting_observer *obs_host, int64_t n, int32_t *order_host);
+
+/* Workspace bytes of siting_viewshed_batch (a work-queue counter and an
+ * error word). */
+size_t siting_viewshed_workspace_size(void);
+
+/* The default schedule for observers with ROI up to rmax. */
+int siting_viewshed_default_schedule(int32_t rmax, siting_schedule *sched_host);
+
+/* Viewsheds of n observers in one persistent launch.  Per observer: rays
+ * from the observer to every boundary cell of its terrain-clipped
+ * (2R+1)^2 window; along each ray, at major-axis step k (k*|minor| =
+ * q*n + r) the terrain sample is S_k = z0*(n-r) + z1*r (n times the linear
+ * interpolation between the posts at minor offsets q and q+1), the marked
+ * cell is the one at minor offset q + [2r >= n] (nearest, ties away from the
+ * observer), and the ray stops when that cell leaves the ROI disk.  With the
+ * horizon (S_J, J) the cell is visible iff
+ *     (S_k + h_r*n - E*n) * J >= (S_J - E*n) * k,    E = z[obs] + h_t,
+ * and the horizon moves to (S_k, k) iff (S_k - E*n)*J > (S_J - E*n)*k; the
+ * first step has no horizon and is visible.  The observer's own cell is
+ * visible.  The viewshed is the OR over rays.  All comparisons are exact
+ * integer arithmetic (stage Viewshed: walk each line of sight updating a
+ * horizon angle).
+ *   obs     : device array of n observers
+ *   offsets : device int64[n+1] from siting_viewshed_layout
+ *   order   : device int32[n] processing order, or NULL for 0..n-1
+ *   sched_host : schedule, or NULL for siting_viewshed_default_schedule(max roi)
+ *   sink SITING_SINK_BITMAP: bitmaps (device uint64[offsets[n]]) is written;
+ *        visible/cells may be NULL.
+ *   sink SITING_SINK_COUNT : visible[i] = number of visible cells (including
+ *        the observer), cells[i] = number of ROI-disk cells inside the
+ *        terrain (the visibility index is visible/cells, Definitions);
+ *        bitmaps may be NULL and offsets may be NULL.
+ *   rmax    : an upper bound of every observer's roi (sizes LDS).  The
+ *        observer records are not read by the host: a record with roi > rmax
+ *        or any field out of range is skipped (its bitmap words are left
+ *        untouched; sink COUNT writes 0 and 0).
+ *   ws, ws_bytes : workspace of siting_viewshed_workspace_size() bytes. */
+int siting_viewshed_batch(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
+                          const siting_observer *obs, int64_t n, const int64_t *offsets,
+                          const int32_t *order, int32_t rmax,
+                          const siting_schedule *sched_host, int32_t sink,
+                          uint64_t *bitmaps, uint32_t *visible, uint32_t *cells,
+                          void *ws, size_t ws_bytes, void *stream);
+
+/* Times the candidate schedules of siting_viewshed_batch on the given
+ * observers (synchronising the stream) and writes the fastest to
+ * best_host; every candidate produces the same bits.  times_ms_host (may be
+ * NULL) receives up to max_times timings in the order of
+ * siting_autotune_candidates.  bitmaps must hold offsets[n] words. */
+int siting_autotune(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
+                    const siting_observer *obs, int64_t n, const int64_t *offsets,
+                    const int32_t *order, int32_t rmax, uint64_t *bitmaps, void *ws,
+                    size_t ws_bytes, void *stream, siting_schedule *best_host,
+                    float *times_ms_host, int32_t max_times);
+
+/* Host-only: the candidate schedules the autotuner tries for rmax. */
+int siting_autotune_candidates(int32_t rmax, siting_schedule *out_host, int32_t max_out);
+
+/* --------------------------------------------------------------- SITE ----
+ * Greedy observer selection (stage Site): starting from an empty cumulative
+ * viewshed C, repeatedly take the candidate with the largest gain
+ * |V_i \ C| (ties to the smallest candidate index), record it and set
+ * C |= V_i; stop after max_obs observers, once |C| >= target_cells, or
+ * when the best gain is 0.  Evaluated lazily: a stale gain is an upper bound
+ * of the current one (the stage's stated optimisation), so the selection is
+ * exactly the plain greedy one.
+ *   bitmaps/offsets/obs : as produced by siting_viewshed_batch (device)
+ *   n < 2^32; windows must be those of the same nrows x ncols terrain; a
+ *   record with a position or roi out of range counts as gaining nothing
+ *   cumulative : out (device) uint64[nrows * ceil(ncols/64)], overwritten
+ *   selected, gains : out (device) int64[max_obs]; entries past *nselected
+ *                     are left untouched
+ *   nselected  : out (device) int32, number selected
+ *   ws, ws_bytes : workspace of siting_greedy_workspace_size(n) bytes */
+size_t siting_greedy_workspace_size(int64_t n);
+int siting_greedy(const uint64_t *bitmaps, const int64_t *offsets, const siting_observer *obs,
+                  int64_t n, int64_t nrows, int64_t ncols, int32_t max_obs, int64_t target_cells,
+                  uint64_t *cumulative, int64_t *selected, int64_t *gains, int32_t *nselected,
+                  void *ws, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SITING_H */

@@ -1,0 +1,193 @@
+// FINDMAX: the k best posts of every block of a grid_r x grid_c block grid
+// (stage Findmax: blocks of width ROI/3, 20 transmitters kept per block).
+//
+// One workgroup per block.  Each post becomes one unique 64-bit key, larger
+// is better:
+//   u8 keys : count << 56 | (z ^ 0x8000) << 40 | (2^40-1 - local)
+//   f32 keys: ord(score) << 32 | (2^32-1 - local)
+// where local is the row-major index inside the block (same order as the
+// global linear index) and ord() maps floats to order-preserving unsigned
+// integers (NaN as -infinity).  Every lane streams its share of the block
+// keeping a sorted register top-k; a threshold test makes insertions rare.
+// The per-lane lists are then merged by k rounds of a workgroup argmax in
+// which the winning lane pops its list head.
+// HBM-bound: 3 bytes per post (u8 key + int16 z), read once, coalesced.
+#include "common.hpp"
+
+namespace siting {
+namespace {
+
+constexpr int kFmThreads = 256;
+constexpr int kFmMaxK = 32;
+
+__device__ __forceinline__ uint32_t ord_f32(float f)
+{
+    uint32_t b = __float_as_uint(f);
+    if (f != f)
+        b = 0xFF800000u;  // NaN ranks as -infinity
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        uint64_t w = __shfl_xor(v, o, 64);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+// Per-lane sorted (descending) list of the KMAX largest keys seen; keeping
+// KMAX >= k per lane is a superset of the lane's top-k, and static indexing
+// keeps the list in registers.
+template <int KMAX>
+__device__ __forceinline__ void topk_insert(uint64_t (&top)[KMAX], uint64_t key)
+{
+    if (key <= top[KMAX - 1])
+        return;
+    uint64_t cur = key;
+#pragma unroll
+    for (int i = 0; i < KMAX; i++) {
+        uint64_t hi = cur > top[i] ? cur : top[i];
+        uint64_t lo = cur > top[i] ? top[i] : cur;
+        top[i] = hi;
+        cur = lo;
+    }
+}
+
+template <int KMAX, bool kF32>
+__global__ __launch_bounds__(kFmThreads) void findmax_kernel(
+    const void *__restrict__ keyp, int stride, const int16_t *__restrict__ z, int64_t nrows,
+    int64_t ncols, int64_t ld, int grid_r, int grid_c, int k, int64_t *__restrict__ cand)
+{
+    __shared__ uint64_t wmax[kFmThreads / 64];
+    int64_t blk = blockIdx.x;
+    int bi = (int)(blk / grid_c), bj = (int)(blk % grid_c);
+    int64_t r0 = (int64_t)bi * nrows / grid_r, r1 = (int64_t)(bi + 1) * nrows / grid_r;
+    int64_t c0 = (int64_t)bj * ncols / grid_c, c1 = (int64_t)(bj + 1) * ncols / grid_c;
+    uint64_t top[KMAX];
+#pragma unroll
+    for (int i = 0; i < KMAX; i++)
+        top[i] = 0;  // 0 is below every valid key
+    int tid = threadIdx.x;
+    int64_t lr0, lr1, lc0, lc1;  // rows/cols of the key lattice inside the block
+    if (!kF32) {
+        lr0 = r0; lr1 = r1; lc0 = c0; lc1 = c1;
+    } else {
+        lr0 = (r0 + stride - 1) / stride; lr1 = (r1 + stride - 1) / stride;
+        lc0 = (c0 + stride - 1) / stride; lc1 = (c1 + stride - 1) / stride;
+    }
+    int64_t bw = lc1 - lc0, bh = lr1 - lr0;
+    int64_t kc = kF32 ? (ncols + stride - 1) / stride : ncols;
+    // rows are walked by waves, columns by lanes: coalesced streaming
+    int wave = tid >> 6, lane = tid & 63;
+    for (int64_t row = wave; row < bh; row += kFmThreads / 64) {
+        int64_t ly = lr0 + row;
+        for (int64_t col = lane; col < bw; col += 64) {
+            int64_t lx = lc0 + col;
+            uint64_t local = (uint64_t)(row * bw + col);
+            uint64_t key;
+            if (!kF32) {
+                uint32_t c = ((const uint8_t *)keyp)[ly * ncols + lx];
+                uint32_t zz = (uint16_t)z[ly * ld + lx] ^ 0x8000u;
+                key = ((uint64_t)c << 56) | ((uint64_t)zz << 40) |
+                      (0xFFFFFFFFFFull - local);
+            } else {
+                float f = ((const float *)keyp)[ly * kc + lx];
+                key = ((uint64_t)ord_f32(f) << 32) | (0xFFFFFFFFull - local);
+            }
+            topk_insert<KMAX>(top, key);
+        }
+    }
+    for (int rank = 0; rank < k; rank++) {
+        uint64_t mine = top[0];
+        uint64_t m = wave_max_u64(mine);
+        if (lane == 0)
+            wmax[wave] = m;
+        __syncthreads();
+        uint64_t best = wmax[0];
+#pragma unroll
+        for (int w = 1; w < kFmThreads / 64; w++)
+            best = wmax[w] > best ? wmax[w] : best;
+        // keys are unique: exactly one lane owns a non-zero maximum; it pops
+        // its list head
+        if (best != 0 && mine == best) {
+#pragma unroll
+            for (int i = 0; i + 1 < KMAX; i++)
+                top[i] = top[i + 1];
+            top[KMAX - 1] = 0;
+        }
+        if (tid == 0) {
+            int64_t out = -1;
+            if (best != 0) {
+                uint64_t local = kF32 ? (0xFFFFFFFFull - (best & 0xFFFFFFFFull))
+                                      : (0xFFFFFFFFFFull - (best & 0xFFFFFFFFFFull));
+                int64_t ly = lr0 + (int64_t)(local / (uint64_t)bw);
+                int64_t lx = lc0 + (int64_t)(local % (uint64_t)bw);
+                out = kF32 ? (ly * stride) * ncols + lx * stride : ly * ncols + lx;
+            }
+            cand[blk * k + rank] = out;
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+}  // namespace siting
+
+using namespace siting;
+
+extern "C" int siting_findmax(const void *key, int32_t key_type, int32_t key_stride,
+                              const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
+                              int32_t grid_r, int32_t grid_c, int32_t k, int64_t *cand,
+                              void *stream)
+{
+    clear_error();
+    SITING_REQUIRE(key != nullptr && cand != nullptr, "siting_findmax: NULL key or output");
+    SITING_REQUIRE(key_type == SITING_KEY_U8 || key_type == SITING_KEY_F32,
+                   "siting_findmax: unknown key_type %d", key_type);
+    SITING_REQUIRE(key_type == SITING_KEY_F32 || z != nullptr,
+                   "siting_findmax: u8 keys need the terrain for tie-breaking");
+    SITING_REQUIRE(nrows >= 1 && ncols >= 1, "siting_findmax: empty terrain");
+    SITING_REQUIRE(key_type == SITING_KEY_F32 || ld >= ncols, "siting_findmax: ld < ncols");
+    SITING_REQUIRE(key_stride >= 1, "siting_findmax: key_stride must be >= 1");
+    SITING_REQUIRE(key_type == SITING_KEY_F32 || key_stride == 1,
+                   "siting_findmax: u8 keys need key_stride 1");
+    SITING_REQUIRE(grid_r >= 1 && grid_r <= nrows && grid_c >= 1 && grid_c <= ncols,
+                   "siting_findmax: grid %dx%d does not fit the %lldx%lld terrain", grid_r,
+                   grid_c, (long long)nrows, (long long)ncols);
+    SITING_REQUIRE(k >= 1, "siting_findmax: k must be >= 1");
+    if (k > kFmMaxK) {
+        set_error("siting_findmax: k %d above the supported %d", k, kFmMaxK);
+        return SITING_E_UNSUPPORTED;
+    }
+    int64_t blocks = (int64_t)grid_r * grid_c;
+    int64_t max_block = ((nrows + grid_r - 1) / grid_r) * ((ncols + grid_c - 1) / grid_c);
+    if (blocks > INT32_MAX || (key_type == SITING_KEY_U8 && max_block >= (1ll << 40)) ||
+        (key_type == SITING_KEY_F32 && max_block >= (1ll << 32))) {
+        set_error("siting_findmax: blocks too large or too many");
+        return SITING_E_UNSUPPORTED;
+    }
+    hipStream_t s = as_stream(stream);
+    dim3 g((unsigned)blocks), b(kFmThreads);
+#define FM_LAUNCH(KM)                                                                          \
+    do {                                                                                       \
+        if (key_type == SITING_KEY_U8)                                                         \
+            hipLaunchKernelGGL((findmax_kernel<KM, false>), g, b, 0, s, key, key_stride, z,    \
+                               nrows, ncols, ld, grid_r, grid_c, k, cand);                     \
+        else                                                                                   \
+            hipLaunchKernelGGL((findmax_kernel<KM, true>), g, b, 0, s, key, key_stride, z,     \
+                               nrows, ncols, ld, grid_r, grid_c, k, cand);                     \
+    } while (0)
+    if (k <= 4)
+        FM_LAUNCH(4);
+    else if (k <= 10)
+        FM_LAUNCH(10);
+    else if (k <= 20)
+        FM_LAUNCH(20);
+    else
+        FM_LAUNCH(32);
+#undef FM_LAUNCH
+    return check_launch("findmax_kernel");
+}

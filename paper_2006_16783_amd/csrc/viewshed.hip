@@ -1,0 +1,519 @@
+// VIEWSHED: batched ray-sweep viewsheds in one persistent launch (stage
+// Viewshed: walk around the ROI circle, run a line of sight to each point and
+// walk along it updating a horizon; bitmaps in 64-bit words).
+//
+// Design (gfx950):
+//  * Persistent workgroups pop observers from an atomic queue (the caller's
+//    order, normally longest ROI first), so uneven ROIs balance themselves.
+//  * The observer's window bitmap lives in LDS (rows x words, a row pitch of
+//    an odd number of dwords so column-wise marks hit distinct banks) and is
+//    written to HBM once, coalesced, in the global word alignment.
+//  * The window is swept one quadrant at a time.  Each quadrant's rays read
+//    only posts inside that quadrant, so a workgroup stages a (R+2)^2 int16
+//    quadrant in LDS (rotated into a common local frame, so one ray routine
+//    serves all four), instead of the (2R+1)^2 window: 4x less LDS, 4x more
+//    resident workgroups.  Observers above the schedule's stage_rmax read the
+//    terrain straight from global memory (L2 / Infinity Cache) instead.
+//  * One ray per lane; consecutive lanes take consecutive boundary cells, so
+//    a wavefront's rays have similar lengths and similar LDS rows.
+//  * Exact integer slopes.  The per-quadrant elevation range bounds every
+//    product; when (|z-E|max + h_r) * R^2 < 2^31 (almost always) the comparisons
+//    run on the full-rate 24-bit multiplier in int32, otherwise in int64.
+#include <algorithm>
+#include <type_traits>
+
+#include "common.hpp"
+
+namespace siting {
+namespace {
+
+__device__ __forceinline__ int wave_min_i32(int v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1)
+        v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max_i32(int v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1)
+        v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Geometry of one quadrant in its local frame (u along the quadrant's first
+// axis, v along the second; u > 0, v >= 0).  Global offsets of local (u, v):
+//   Q0: ( u,  v)   Q1: (-v,  u)   Q2: (-u, -v)   Q3: ( v, -u)
+struct Quadrant {
+    int eu, ev;     // extents of the clipped window along u and v
+    int bu, bv;     // bitmap bit-position steps of u and v
+    int gu, gv;     // global terrain element steps of u and v
+};
+
+__device__ __forceinline__ Quadrant make_quadrant(int qd, int ex_p, int ex_m, int ey_p,
+                                                  int ey_m, int BP, int ld)
+{
+    // ex_p = xhi - x, ex_m = x - xlo, ey_p = yhi - y, ey_m = y - ylo
+    Quadrant Q;
+    switch (qd) {
+    case 0: Q.eu = ex_p; Q.ev = ey_p; Q.bu = 1;   Q.bv = BP;  Q.gu = 1;   Q.gv = ld;  break;
+    case 1: Q.eu = ey_p; Q.ev = ex_m; Q.bu = BP;  Q.bv = -1;  Q.gu = ld;  Q.gv = -1;  break;
+    case 2: Q.eu = ex_m; Q.ev = ey_m; Q.bu = -1;  Q.bv = -BP; Q.gu = -1;  Q.gv = -ld; break;
+    default: Q.eu = ey_m; Q.ev = ex_p; Q.bu = -BP; Q.bv = 1;  Q.gu = -ld; Q.gv = 1;   break;
+    }
+    return Q;
+}
+
+// Boundary cell of ray rho (0 <= rho < eu + ev) in the local frame: first the
+// far side u = eu (v = 0..ev), then the far side v = ev (u = eu-1..1).
+__device__ __forceinline__ void ray_target(const Quadrant &Q, int rho, int &du, int &dv)
+{
+    if (rho <= Q.ev) {
+        du = Q.eu;
+        dv = rho;
+    } else {
+        du = Q.eu - (rho - Q.ev);
+        dv = Q.ev;
+    }
+}
+
+// Terrain sources.  `at(off)` reads the post at element offset `off` from the
+// observer (LDS quadrant in the local frame, or the global terrain).
+struct LdsSrc {
+    const int16_t *p;
+    __device__ __forceinline__ int at(int off) const { return p[off]; }
+};
+struct GlobalSrc {
+    const int16_t *p;
+    __device__ __forceinline__ int at(int off) const { return p[off]; }
+};
+
+// Sweep one ray to local boundary cell (du, dv).
+//  zs_u, zs_v : terrain element steps of u and v in `src`
+//  bm         : LDS bitmap (dwords); P0 the observer's bit position
+// kGuardZ1: read the second post only when r > 0 (needed for global reads,
+// where the padding post may lie outside the terrain).
+template <bool kNarrow, bool kGuardZ1, class Src>
+__device__ __forceinline__ void sweep(const Src &src, int zs_u, int zs_v, uint32_t *bm, int P0,
+                                      int bu, int bv, int du, int dv, int R2, int E, int h_r)
+{
+    bool umaj = du >= dv;
+    int n = umaj ? du : dv, mn = umaj ? dv : du;
+    int zs_maj = umaj ? zs_u : zs_v, zs_min = umaj ? zs_v : zs_u;
+    int bs_maj = umaj ? bu : bv, bs_min = umaj ? bv : bu;
+    using W = typename std::conditional<kNarrow, int, long long>::type;
+    int En = E * n;
+    W hrn = (W)h_r * n;
+    // step 1 (no horizon yet)
+    int r = mn, q = 0;
+    if (r >= n) {
+        r -= n;
+        q = 1;
+    }
+    int up = 2 * r >= n;
+    int m = q + up;
+    if (1 + m * m > R2)
+        return;
+    int zi = zs_maj + q * zs_min;
+    int bq = P0 + bs_maj + q * bs_min;
+    int z0 = src.at(zi);
+    int z1 = (!kGuardZ1 || r) ? src.at(zi + zs_min) : 0;
+    int S = __mul24(z0, n) + __mul24(z1 - z0, r);
+    int T = S - En;
+    {
+        int bp = bq + (up ? bs_min : 0);
+        atomicOr(&bm[bp >> 5], 1u << (bp & 31));
+    }
+    // horizon (hN, hJ): slope hN / hJ; B = hN * k for the current k
+    W hN = T, hJ = 1, hrnJ = hrn, B = T;
+    int k2 = 1;
+    for (int k = 2; k <= n; k++) {
+        r += mn;
+        zi += zs_maj;
+        bq += bs_maj;
+        k2 += 2 * k - 1;
+        if (r >= n) {
+            r -= n;
+            zi += zs_min;
+            bq += bs_min;
+            q++;
+        }
+        up = 2 * r >= n;
+        m = q + up;
+        if (k2 + __mul24(m, m) > R2)
+            break;
+        z0 = src.at(zi);
+        z1 = (!kGuardZ1 || r) ? src.at(zi + zs_min) : 0;
+        S = __mul24(z0, n) + __mul24(z1 - z0, r);
+        T = S - En;
+        B += hN;
+        W PT, PV;
+        if (kNarrow) {
+            PT = __mul24((int)T, (int)hJ);
+        } else {
+            PT = (W)T * hJ;
+        }
+        PV = PT + hrnJ;
+        if (PV >= B) {
+            int bp = bq + (up ? bs_min : 0);
+            atomicOr(&bm[bp >> 5], 1u << (bp & 31));
+        }
+        if (PT > B) {
+            hN = T;
+            hJ = k;
+            if (kNarrow) {
+                hrnJ = __mul24((int)hrn, k);
+                B = __mul24(T, k);
+            } else {
+                hrnJ = hrn * k;
+                B = (W)T * k;
+            }
+        }
+    }
+}
+
+// LDS layout helpers (bytes), shared by host sizing and the kernel.
+__host__ __device__ __forceinline__ int bm_pitch_dw(int rmax)
+{
+    int nw = ((2 * rmax) >> 6) + 2;  // max 64-bit words a window row spans
+    return 2 * nw + 1;               // odd dword pitch
+}
+__host__ __device__ __forceinline__ int bm_bytes(int rmax)
+{
+    return (2 * rmax + 1) * bm_pitch_dw(rmax) * 4;
+}
+__host__ __device__ __forceinline__ int zq_pitch(int rmax)
+{
+    int p = (rmax + 2 + 1) & ~1;  // even element count ...
+    if (((p >> 1) & 1) == 0)      // ... whose dword count is odd
+        p += 2;
+    return p;
+}
+__host__ __device__ __forceinline__ int zq_bytes(int rmax)
+{
+    return rmax > 0 ? (rmax + 2) * zq_pitch(rmax) * 2 : 0;
+}
+
+__global__ void viewshed_queue_reset(uint32_t *queue) { queue[0] = 0; }
+
+__device__ __forceinline__ int isqrt_floor(int v)
+{
+    int s = (int)sqrtf((float)v);
+    while (s > 0 && s * s > v)
+        s--;
+    while ((s + 1) * (s + 1) <= v)
+        s++;
+    return s;
+}
+
+__global__ void viewshed_kernel(const int16_t *__restrict__ z, int64_t nrows, int64_t ncols,
+                                int64_t ld, const siting_observer *__restrict__ obs, int64_t n,
+                                const int64_t *__restrict__ offsets,
+                                const int32_t *__restrict__ order, int sink,
+                                uint64_t *__restrict__ bitmaps, uint32_t *__restrict__ visible,
+                                uint32_t *__restrict__ cells, uint32_t *queue, int rmax,
+                                int stage_rmax)
+{
+    extern __shared__ uint32_t lds[];
+    __shared__ int64_t s_task;
+    __shared__ int s_red[2 * 16];
+    __shared__ uint32_t s_sum[2 * 16];
+    const int tid = threadIdx.x, nthreads = blockDim.x;
+    const int wave = tid >> 6, lane = tid & 63, nwaves = nthreads >> 6;
+    uint32_t *bm = lds;
+    int16_t *zq = reinterpret_cast<int16_t *>(lds + bm_bytes(rmax) / 4);
+    const int zp = zq_pitch(stage_rmax);
+    const int BPdw = bm_pitch_dw(rmax);
+    const int BP = BPdw * 32;
+
+    for (;;) {
+        if (tid == 0)
+            s_task = atomicAdd(queue, 1u);
+        __syncthreads();
+        int64_t task = s_task;
+        if (task >= n)
+            break;
+        int64_t i = order ? order[task] : task;
+        siting_observer o = obs[i];
+        // records the host did not validate: never touch memory for them
+        if (o.roi < 1 || o.roi > rmax || o.x < 0 || o.x >= ncols || o.y < 0 || o.y >= nrows ||
+            o.h_t < 0 || o.h_t > kMaxHeight || o.h_r < 0 || o.h_r > kMaxHeight) {
+            if (sink == SITING_SINK_COUNT && tid == 0) {
+                visible[i] = 0;
+                cells[i] = 0;
+            }
+            __syncthreads();
+            continue;
+        }
+        const int R = o.roi;
+        const int64_t x = o.x, y = o.y;
+        const int64_t xlo = x - R < 0 ? 0 : x - R, xhi = x + R > ncols - 1 ? ncols - 1 : x + R;
+        const int64_t ylo = y - R < 0 ? 0 : y - R, yhi = y + R > nrows - 1 ? nrows - 1 : y + R;
+        const int64_t w0 = xlo >> 6;
+        const int nw = (int)((xhi >> 6) - w0 + 1);
+        const int rows = (int)(yhi - ylo + 1);
+        const int ex_p = (int)(xhi - x), ex_m = (int)(x - xlo);
+        const int ey_p = (int)(yhi - y), ey_m = (int)(y - ylo);
+        const int P0 = (int)(y - ylo) * BP + (int)(x - (w0 << 6));
+        const int R2 = R * R;
+        const int16_t *zo = z + y * ld + x;
+        const int E = (int)zo[0] + o.h_t;
+
+        for (int e = tid; e < rows * BPdw; e += nthreads)
+            bm[e] = 0;
+        __syncthreads();
+        if (tid == 0)
+            atomicOr(&bm[P0 >> 5], 1u << (P0 & 31));
+
+        if (R <= stage_rmax) {
+            for (int qd = 0; qd < 4; qd++) {
+                Quadrant Q = make_quadrant(qd, ex_p, ex_m, ey_p, ey_m, BP, (int)ld);
+                if (Q.eu < 1)
+                    continue;
+                // stage local (u, v) in [0, eu] x [0, ev] from the quadrant's
+                // global box, row by row (coalesced global reads)
+                int64_t gx0, gx1, gy0, gy1;
+                switch (qd) {
+                case 0: gx0 = x;         gx1 = x + Q.eu; gy0 = y;         gy1 = y + Q.ev; break;
+                case 1: gx0 = x - Q.ev;  gx1 = x;        gy0 = y;         gy1 = y + Q.eu; break;
+                case 2: gx0 = x - Q.eu;  gx1 = x;        gy0 = y - Q.ev;  gy1 = y;        break;
+                default: gx0 = x;        gx1 = x + Q.ev; gy0 = y - Q.eu;  gy1 = y;        break;
+                }
+                int zmin = 32767, zmax = -32768;
+                const int bw = (int)(gx1 - gx0 + 1), bh = (int)(gy1 - gy0 + 1);
+                for (int row = wave; row < bh; row += nwaves) {
+                    const int16_t *src = z + (gy0 + row) * ld + gx0;
+                    const int gy = (int)(gy0 + row - y);
+                    for (int col = lane; col < bw; col += 64) {
+                        int v = src[col];
+                        int gx = (int)(gx0 + col - x);
+                        int lu, lv;
+                        switch (qd) {
+                        case 0: lu = gx;  lv = gy;  break;
+                        case 1: lu = gy;  lv = -gx; break;
+                        case 2: lu = -gx; lv = -gy; break;
+                        default: lu = -gy; lv = gx; break;
+                        }
+                        zq[lv * zp + lu] = (int16_t)v;
+                        zmin = min(zmin, v);
+                        zmax = max(zmax, v);
+                    }
+                }
+                zmin = wave_min_i32(zmin);
+                zmax = wave_max_i32(zmax);
+                if (lane == 0) {
+                    s_red[wave] = zmin;
+                    s_red[16 + wave] = zmax;
+                }
+                __syncthreads();
+                int gmin = s_red[0], gmax = s_red[16];
+                for (int w = 1; w < nwaves; w++) {
+                    gmin = min(gmin, s_red[w]);
+                    gmax = max(gmax, s_red[16 + w]);
+                }
+                long long D = max((long long)gmax - E, (long long)E - gmin) + o.h_r;
+                bool narrow = D * R < (1ll << 23) && D * R * R < (1ll << 31);
+                LdsSrc src{zq};
+                const int nrays = Q.eu + Q.ev;
+                for (int rho = tid; rho < nrays; rho += nthreads) {
+                    int du, dv;
+                    ray_target(Q, rho, du, dv);
+                    if (narrow)
+                        sweep<true, false>(src, 1, zp, bm, P0, Q.bu, Q.bv, du, dv, R2, E, o.h_r);
+                    else
+                        sweep<false, false>(src, 1, zp, bm, P0, Q.bu, Q.bv, du, dv, R2, E, o.h_r);
+                }
+                __syncthreads();
+            }
+        } else {
+            // global terrain reads; the four quadrants' rays in one pass
+            int n0 = ex_p >= 1 ? ex_p + ey_p : 0;
+            int n1 = n0 + (ey_p >= 1 ? ey_p + ex_m : 0);
+            int n2 = n1 + (ex_m >= 1 ? ex_m + ey_m : 0);
+            int n3 = n2 + (ey_m >= 1 ? ey_m + ex_p : 0);
+            GlobalSrc src{zo};
+            for (int rho = tid; rho < n3; rho += nthreads) {
+                int qd = rho < n0 ? 0 : rho < n1 ? 1 : rho < n2 ? 2 : 3;
+                int base = qd == 0 ? 0 : qd == 1 ? n0 : qd == 2 ? n1 : n2;
+                Quadrant Q = make_quadrant(qd, ex_p, ex_m, ey_p, ey_m, BP, (int)ld);
+                int du, dv;
+                ray_target(Q, rho - base, du, dv);
+                sweep<false, true>(src, Q.gu, Q.gv, bm, P0, Q.bu, Q.bv, du, dv, R2, E, o.h_r);
+            }
+            __syncthreads();
+        }
+
+        if (sink == SITING_SINK_BITMAP) {
+            uint64_t *out = bitmaps + offsets[i];
+            const int words = rows * nw;
+            for (int e = tid; e < words; e += nthreads) {
+                int row = e / nw, w = e - row * nw;
+                const uint32_t *src = bm + row * BPdw + 2 * w;
+                out[e] = (uint64_t)src[0] | ((uint64_t)src[1] << 32);
+            }
+        } else {
+            uint32_t vis = 0, cnt = 0;
+            for (int e = tid; e < rows * BPdw; e += nthreads)
+                vis += __popc(bm[e]);
+            for (int row = tid; row < rows; row += nthreads) {
+                int dy = (int)(ylo + row - y);
+                int half = isqrt_floor(R2 - dy * dy);
+                int64_t a = x - half < xlo ? xlo : x - half;
+                int64_t b = x + half > xhi ? xhi : x + half;
+                if (b >= a)
+                    cnt += (uint32_t)(b - a + 1);
+            }
+            vis = wave_sum_u32(vis);
+            cnt = wave_sum_u32(cnt);
+            if (lane == 0) {
+                s_sum[wave] = vis;
+                s_sum[16 + wave] = cnt;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                uint32_t tv = 0, tc = 0;
+                for (int w = 0; w < nwaves; w++) {
+                    tv += s_sum[w];
+                    tc += s_sum[16 + w];
+                }
+                visible[i] = tv;
+                cells[i] = tc;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+int lds_bytes_for(int rmax, int stage_rmax)
+{
+    return bm_bytes(rmax) + zq_bytes(std::min(stage_rmax, rmax));
+}
+
+}  // namespace
+
+int viewshed_launch(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
+                    const siting_observer *obs, int64_t n, const int64_t *offsets,
+                    const int32_t *order, int32_t rmax, const siting_schedule &sc, int32_t sink,
+                    uint64_t *bitmaps, uint32_t *visible, uint32_t *cells, void *ws,
+                    hipStream_t s)
+{
+    int stage = std::min(sc.stage_rmax, rmax);
+    int lds = lds_bytes_for(rmax, stage);
+    if (lds > device_max_lds()) {
+        set_error("siting_viewshed_batch: schedule needs %d bytes of LDS (device max %d)", lds,
+                  device_max_lds());
+        return SITING_E_UNSUPPORTED;
+    }
+    int64_t grid = (int64_t)device_cus() * sc.groups_per_cu;
+    if (grid > n)
+        grid = n;
+    uint32_t *queue = reinterpret_cast<uint32_t *>(ws);
+    hipLaunchKernelGGL(viewshed_queue_reset, dim3(1), dim3(1), 0, s, queue);
+    int rc = check_launch("viewshed_queue_reset");
+    if (rc != SITING_OK)
+        return rc;
+    if (grid <= 0)
+        return SITING_OK;
+    hipLaunchKernelGGL(viewshed_kernel, dim3((unsigned)grid), dim3(64 * sc.waves), (size_t)lds, s,
+                       z, nrows, ncols, ld, obs, n, offsets, order, sink, bitmaps, visible, cells,
+                       queue, rmax, stage);
+    return check_launch("viewshed_kernel");
+}
+
+int viewshed_default_schedule(int32_t rmax, siting_schedule *sc)
+{
+    const int budget = 160 * 1024;
+    sc->reserved = 0;
+    sc->waves = 4;
+    int lds_staged = lds_bytes_for(rmax, rmax);
+    if (rmax <= 160 && lds_staged <= std::min(budget, device_max_lds())) {
+        sc->stage_rmax = rmax;
+        sc->groups_per_cu = std::max(1, std::min(8, budget / lds_staged));
+    } else {
+        sc->stage_rmax = 0;
+        sc->waves = 8;
+        sc->groups_per_cu = std::max(1, std::min(8, budget / bm_bytes(rmax)));
+    }
+    return SITING_OK;
+}
+
+int viewshed_lds_bytes(int32_t rmax, int32_t stage_rmax) { return lds_bytes_for(rmax, stage_rmax); }
+
+int validate_schedule(const siting_schedule &sc, const char *fn)
+{
+    SITING_REQUIRE(sc.waves >= 1 && sc.waves <= 16, "%s: schedule waves %d outside 1..16", fn,
+                   sc.waves);
+    SITING_REQUIRE(sc.groups_per_cu >= 1 && sc.groups_per_cu <= 16,
+                   "%s: schedule groups_per_cu %d outside 1..16", fn, sc.groups_per_cu);
+    SITING_REQUIRE(sc.stage_rmax >= 0 && sc.stage_rmax <= kMaxRoi,
+                   "%s: schedule stage_rmax out of range", fn);
+    SITING_REQUIRE(sc.reserved == 0, "%s: schedule reserved field must be 0", fn);
+    return SITING_OK;
+}
+
+
+}  // namespace siting
+
+using namespace siting;
+
+extern "C" size_t siting_viewshed_workspace_size(void) { return 256; }
+
+extern "C" int siting_viewshed_default_schedule(int32_t rmax, siting_schedule *sched_host)
+{
+    clear_error();
+    SITING_REQUIRE(sched_host != nullptr, "siting_viewshed_default_schedule: NULL output");
+    SITING_REQUIRE(rmax >= 1 && rmax <= kMaxRoi, "siting_viewshed_default_schedule: bad rmax");
+    return viewshed_default_schedule(rmax, sched_host);
+}
+
+extern "C" int siting_viewshed_batch(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
+                                     const siting_observer *obs, int64_t n, const int64_t *offsets,
+                                     const int32_t *order, int32_t rmax,
+                                     const siting_schedule *sched_host, int32_t sink,
+                                     uint64_t *bitmaps, uint32_t *visible, uint32_t *cells,
+                                     void *ws, size_t ws_bytes, void *stream)
+{
+    clear_error();
+    const char *fn = "siting_viewshed_batch";
+    SITING_REQUIRE(n >= 0 && n <= INT32_MAX, "%s: n out of range", fn);
+    SITING_REQUIRE(nrows >= 1 && ncols >= 1, "%s: empty terrain", fn);
+    SITING_REQUIRE(ld >= ncols, "%s: ld < ncols", fn);
+    SITING_REQUIRE(rmax >= 1 && rmax <= kMaxRoi, "%s: rmax %d outside 1..%d", fn, rmax, kMaxRoi);
+    SITING_REQUIRE(sink == SITING_SINK_BITMAP || sink == SITING_SINK_COUNT, "%s: bad sink", fn);
+    if (n == 0)
+        return SITING_OK;
+    SITING_REQUIRE(z != nullptr && obs != nullptr, "%s: NULL terrain or observers", fn);
+    SITING_REQUIRE(sink != SITING_SINK_BITMAP || (bitmaps != nullptr && offsets != nullptr),
+                   "%s: bitmap sink needs bitmaps and offsets", fn);
+    SITING_REQUIRE(sink != SITING_SINK_COUNT || (visible != nullptr && cells != nullptr),
+                   "%s: count sink needs visible and cells", fn);
+    if (ws == nullptr || ws_bytes < siting_viewshed_workspace_size()) {
+        set_error("%s: workspace of %zu bytes needed", fn, siting_viewshed_workspace_size());
+        return SITING_E_WORKSPACE;
+    }
+    if ((int64_t)(rmax + 2) * ld >= ((int64_t)1 << 31)) {
+        set_error("%s: rmax*ld too large for 32-bit offsets", fn);
+        return SITING_E_UNSUPPORTED;
+    }
+    siting_schedule sc;
+    if (sched_host) {
+        sc = *sched_host;
+        int rc = validate_schedule(sc, fn);
+        if (rc != SITING_OK)
+            return rc;
+    } else {
+        viewshed_default_schedule(rmax, &sc);
+    }
+    return viewshed_launch(z, nrows, ncols, ld, obs, n, offsets, order, rmax, sc, sink, bitmaps,
+                           visible, cells, ws, as_stream(stream));
+}

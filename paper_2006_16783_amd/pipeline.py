@@ -1,0 +1,156 @@
+"""Siting pipeline driver: VIX -> FINDMAX -> VIEWSHED -> SITE on one GPU
+(section "The multiple transmitter siting process").
+
+Host logic only: it chains the C-ABI calls of libsiting on torch's current
+stream, moves the small candidate list to the host to build observer
+records and the bitmap layout, and times every stage with events on that
+stream (the paper's table rows: estimated visibility indexes, potential
+transmitters, viewsheds, top transmitters).
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field, asdict
+
+import numpy as np
+
+from . import _lib as L
+
+
+@dataclass
+class SitingConfig:
+    name: str
+    n: int                 # terrain side (square terrains)
+    beta: float            # fBm spectral exponent
+    zmax: int              # elevation range 0..zmax
+    seed: int              # terrain seed
+    roi: int
+    h_t: int
+    h_r: int
+    K: int                 # VIX receivers per post
+    grid: int              # FINDMAX blocks per side
+    k: int                 # candidates kept per block
+    max_obs: int           # SITE observer cap
+    target_frac: float     # SITE coverage target (fraction of all posts)
+    vix_seed: int = 12345
+
+    def to_dict(self):
+        return asdict(self)
+
+
+# The workloads the build is measured and tested on (square fBm terrains).
+CONFIGS = {
+    # 1000^2, ROI 100, 10x10 blocks of 10 candidates, SITE to 100 observers
+    "plain_1000": SitingConfig("plain_1000", 1000, 2.4, 1000, 1, 100, 10, 10, 10, 10, 10, 100, 1.0),
+    # 4096^2, ROI 200, 50 receivers, 50x50 blocks x 4 = 10000 tentative
+    # observers, SITE to 2000 observers or 90% coverage
+    "batched_4096": SitingConfig("batched_4096", 4096, 2.4, 2000, 1, 200, 10, 10, 50, 50, 4,
+                                 2000, 0.90),
+    # 46400^2 (2.15e9 posts), ROI 100, 64x64 blocks x 20, SITE to 4096
+    "full_46400": SitingConfig("full_46400", 46400, 2.4, 4000, 1, 100, 10, 10, 10, 64, 20,
+                               4096, 1.0),
+}
+
+
+@dataclass
+class SitingResult:
+    selected: np.ndarray
+    gains: np.ndarray
+    candidates: np.ndarray
+    observers: np.ndarray
+    offsets: np.ndarray
+    coverage_cells: int
+    stage_ms: dict = field(default_factory=dict)
+    cell_tests: int = 0
+    schedule: tuple | None = None
+
+
+def target_cells(frac: float, nrows: int, ncols: int) -> int:
+    if frac >= 1.0:
+        return nrows * ncols
+    return int(math.ceil(frac * nrows * ncols))
+
+
+def disk_cell_counts(obs: np.ndarray, nrows: int, ncols: int) -> np.ndarray:
+    """In-terrain ROI-disk cells per observer (the cell-tests of a viewshed),
+    counted row by row on the host for the throughput metric."""
+    out = np.zeros(len(obs), np.int64)
+    for R in np.unique(obs["roi"]):
+        sel = np.nonzero(obs["roi"] == R)[0]
+        dy = np.arange(-R, R + 1)
+        half = np.floor(np.sqrt(np.maximum(R * R - dy * dy, 0))).astype(np.int64)
+        # exact integer square root correction
+        half -= (half * half > R * R - dy * dy)
+        half += ((half + 1) * (half + 1) <= R * R - dy * dy)
+        x = obs["x"][sel].astype(np.int64)[:, None]
+        y = obs["y"][sel].astype(np.int64)[:, None]
+        rows = y + dy[None, :]
+        lo = np.maximum(x - half[None, :], 0)
+        hi = np.minimum(x + half[None, :], ncols - 1)
+        cnt = np.where((rows >= 0) & (rows < nrows), np.maximum(hi - lo + 1, 0), 0)
+        out[sel] = cnt.sum(axis=1)
+    return out
+
+
+class _Timer:
+    def __init__(self, enabled=True):
+        import torch
+        self.torch = torch
+        self.enabled = enabled
+        self.events = []
+
+    def mark(self, name):
+        if not self.enabled:
+            return
+        e = self.torch.cuda.Event(enable_timing=True)
+        e.record()
+        self.events.append((name, e))
+
+    def result(self):
+        if not self.enabled or len(self.events) < 2:
+            return {}
+        self.events[-1][1].synchronize()
+        out = {}
+        for (n0, e0), (_, e1) in zip(self.events[:-1], self.events[1:]):
+            out[n0] = e0.elapsed_time(e1)
+        return out
+
+
+def run(z, cfg: SitingConfig, key=None, key_stride=1, sched=None, timing=True,
+        ws_cache: dict | None = None) -> SitingResult:
+    """One pass of the whole siting path over the device terrain z (int16,
+    resident in HBM).  `key` (float32 device tensor) replaces the VIX count
+    as the FINDMAX ranking when given (surrogate ranking)."""
+    import torch
+    nrows, ncols = z.shape
+    dev = z.device
+    T = _Timer(timing)
+    T.mark("vix" if key is None else "score")
+    if key is None:
+        key = L.siting_vix(z, cfg.roi, cfg.h_t, cfg.h_r, cfg.K, cfg.vix_seed)
+    T.mark("findmax")
+    cand = L.siting_findmax(key, z, cfg.grid, cfg.grid, cfg.k, key_stride=key_stride)
+    T.mark("layout")
+    cand_h = cand.cpu().numpy()
+    cand_h = cand_h[cand_h >= 0]
+    obs = np.zeros(len(cand_h), L.OBSERVER_DTYPE)
+    obs["x"] = cand_h % ncols
+    obs["y"] = cand_h // ncols
+    obs["roi"], obs["h_t"], obs["h_r"] = cfg.roi, cfg.h_t, cfg.h_r
+    off = L.siting_viewshed_layout(obs, nrows, ncols)
+    obs_d = L.observers_to_device(obs, dev)
+    off_d = torch.from_numpy(off).to(dev)
+    T.mark("viewshed")
+    bm = L.siting_viewshed_batch(z, obs_d, off_d, cfg.roi, sched=sched)
+    T.mark("site")
+    sel, gains, nsel, cum = L.siting_greedy(bm, off_d, obs_d, nrows, ncols, cfg.max_obs,
+                                            target_cells(cfg.target_frac, nrows, ncols))
+    T.mark("d2h")
+    m = int(nsel.item())
+    sel_h = sel[:m].cpu().numpy()
+    gains_h = gains[:m].cpu().numpy()
+    T.mark("end")
+    return SitingResult(selected=sel_h, gains=gains_h, candidates=cand_h, observers=obs,
+                        offsets=off, coverage_cells=int(gains_h.sum()), stage_ms=T.result(),
+                        schedule=None if sched is None else sched.as_tuple())

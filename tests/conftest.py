@@ -3,6 +3,9 @@ import sys
 
 import pytest
 
+# load torch's HIP runtime before anything loads libsiting.so
+import torch  # noqa: F401,E402
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)

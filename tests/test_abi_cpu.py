@@ -1,0 +1,92 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/siting.h declares, validates arguments before any
+launch, and its host-only layout/order helpers agree with the oracle."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2006_16783_amd as S
+from paper_2006_16783_amd import _lib as L
+from synth import uniform_observers
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    hdr = open(os.path.join(ROOT, "include", "siting.h")).read()
+    declared = set(re.findall(r"\b(siting_\w+)\s*\(", hdr))
+    assert declared, "no declarations parsed"
+    lib = L.lib()
+    for name in sorted(declared):
+        assert hasattr(lib, name), name
+    assert declared == set(L.EXPORTED)
+    assert S.siting_abi_version() == 1
+
+
+def test_validation_errors_before_launch():
+    lib = L.lib()
+    assert lib.siting_vix(None, 10, 10, 10, 5, 1, 1, 4, 0, None, None) == -1
+    assert "NULL" in L.last_error()
+    fake = 0x1000  # never dereferenced: validation fails first
+    assert lib.siting_vix(fake, 1, 10, 10, 5, 1, 1, 4, 0, fake, None) == -1
+    assert lib.siting_vix(fake, 10, 10, 9, 5, 1, 1, 4, 0, fake, None) == -1
+    assert lib.siting_vix(fake, 10, 10, 10, 0, 1, 1, 4, 0, fake, None) == -1
+    assert lib.siting_vix(fake, 10, 10, 10, 5, -1, 1, 4, 0, fake, None) == -1
+    assert lib.siting_vix(fake, 10, 10, 10, 5, 1, 1, 0, 0, fake, None) == -1
+    assert lib.siting_vix(fake, 10, 10, 10, 5, 1, 1, 256, 0, fake, None) == -1
+    assert lib.siting_findmax(fake, 2, 1, fake, 10, 10, 10, 2, 2, 3, fake, None) == -1
+    assert lib.siting_findmax(fake, 0, 1, fake, 10, 10, 10, 11, 2, 3, fake, None) == -1
+    assert lib.siting_findmax(fake, 0, 2, fake, 10, 10, 10, 2, 2, 3, fake, None) == -1
+    assert lib.siting_findmax(fake, 0, 1, fake, 10, 10, 10, 2, 2, 33, fake, None) == -2
+    # viewshed: missing workspace, bad sink, bad schedule
+    assert lib.siting_viewshed_batch(fake, 10, 10, 10, fake, 3, fake, None, 5, None, 0,
+                                     fake, None, None, None, 0, None) == -4
+    assert lib.siting_viewshed_batch(fake, 10, 10, 10, fake, 3, fake, None, 5, None, 7,
+                                     fake, None, None, fake, 256, None) == -1
+    bad = L.Schedule(0, 1, 0, 0)
+    import ctypes
+    assert lib.siting_viewshed_batch(fake, 10, 10, 10, fake, 3, fake, None, 5, ctypes.byref(bad),
+                                     0, fake, None, None, fake, 256, None) == -1
+    assert "waves" in L.last_error()
+    # greedy: workspace too small
+    assert lib.siting_greedy(fake, fake, fake, 5, 10, 10, 3, 100, fake, fake, fake, fake,
+                             fake, 8, None) == -4
+    assert lib.siting_greedy(fake, fake, fake, 0, 10, 10, 3, 100, fake, fake, fake, fake,
+                             fake, 1 << 20, None) == -1
+
+
+def test_layout_matches_oracle_and_rejects_bad_observers(orc):
+    for (nr, nc, seed) in [(100, 130, 1), (64, 64, 2), (7, 300, 3)]:
+        obs = uniform_observers(nr, nc, 50, seed, roi=(1, 90), height=(0, 30))
+        assert (S.siting_viewshed_layout(obs, nr, nc) == orc.layout(obs, nr, nc)).all()
+    obs = uniform_observers(50, 50, 5, 1, roi=(1, 10))
+    bad = obs.copy()
+    bad["x"][2] = 50
+    with pytest.raises(S.SitingError):
+        S.siting_viewshed_layout(bad, 50, 50)
+    bad = obs.copy()
+    bad["roi"][0] = 0
+    with pytest.raises(S.SitingError):
+        S.siting_viewshed_layout(bad, 50, 50)
+    bad = obs.copy()
+    bad["h_r"][1] = -3
+    with pytest.raises(S.SitingError):
+        S.siting_viewshed_layout(bad, 50, 50)
+
+
+def test_order_is_longest_first_permutation():
+    obs = uniform_observers(500, 500, 300, 4, roi=(50, 400))
+    order = S.siting_viewshed_order(obs)
+    assert sorted(order.tolist()) == list(range(300))
+    r = obs["roi"][order]
+    assert (np.diff(r) <= 0).all()
+
+
+def test_autotune_candidates_bit_identical_contract():
+    c = S.siting_autotune_candidates(100)
+    assert len(c) >= 2
+    assert any(s.stage_rmax == 100 for s in c) and any(s.stage_rmax == 0 for s in c)
+    big = S.siting_autotune_candidates(400)
+    assert all(s.stage_rmax in (0, 400) for s in big)

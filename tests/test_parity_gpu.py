@@ -1,0 +1,213 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle: bit-exact
+on seeded fBm terrains, at sizes that span several tiles with ragged tails,
+clipped edge windows and uneven ROIs."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def S():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2006_16783_amd as S
+    return S
+
+
+def _terrain(n, beta, zmax, seed, ncols=None):
+    from synth import fbm
+    return fbm(n, beta, zmax, seed, ncols=ncols)
+
+
+def _u64(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+# ---------------------------------------------------------------- VIX ------
+@pytest.mark.parametrize("shape,R,ht,hr,K,seed", [
+    ((300, 257), 20, 10, 10, 10, 1),     # LDS tiles with ragged edges
+    ((130, 517), 7, 0, 0, 255, 99),      # K at its maximum, zero heights
+    ((64, 64), 100, 10, 10, 10, 5),      # ROI larger than the terrain
+    ((421, 380), 140, 25, 3, 6, 7),      # too big for an LDS tile: global reads
+])
+def test_vix_parity(S, orc, shape, R, ht, hr, K, seed):
+    _say("vix", shape, R, ht, hr, K, seed)
+    z = _terrain(shape[0], 2.4, 1500, seed, ncols=shape[1])
+    zd = torch.from_numpy(z).cuda()
+    got = S.siting_vix(zd, R, ht, hr, K, seed * 7919).cpu().numpy()
+    want = orc.vix(z, R, ht, hr, K, seed * 7919)
+    assert (got == want).all(), int((got != want).sum())
+
+
+def test_vix_strided_terrain(S, orc):
+    z = _terrain(200, 2.2, 800, 3, ncols=300)
+    big = torch.zeros((200, 320), dtype=torch.int16, device="cuda")
+    big[:, :300] = torch.from_numpy(z).cuda()
+    got = S.siting_vix(big[:, :300], 15, 5, 5, 9, 4).cpu().numpy()
+    assert (got == orc.vix(z, 15, 5, 5, 9, 4)).all()
+
+
+# ------------------------------------------------------------ FINDMAX ------
+@pytest.mark.parametrize("shape,g_r,g_c,k", [((1000, 1000), 10, 10, 10), ((333, 517), 7, 3, 20),
+                                            ((97, 101), 97, 101, 1), ((250, 250), 4, 4, 32)])
+def test_findmax_u8_parity(S, orc, shape, g_r, g_c, k):
+    _say("findmax", shape, g_r, g_c, k)
+    rng = np.random.default_rng(k)
+    z = _terrain(shape[0], 2.4, 500, 11, ncols=shape[1])
+    key = rng.integers(0, 11, size=shape).astype(np.uint8)
+    got = S.siting_findmax(torch.from_numpy(key).cuda(), torch.from_numpy(z).cuda(), g_r, g_c,
+                           k).cpu().numpy()
+    assert (got == orc.findmax(key, z, g_r, g_c, k)).all()
+
+
+@pytest.mark.parametrize("stride", [1, 3, 4])
+def test_findmax_f32_parity(S, orc, stride):
+    z = _terrain(410, 2.4, 500, 12, ncols=390)
+    kr, kc = -(-410 // stride), -(-390 // stride)
+    rng = np.random.default_rng(stride)
+    sc = rng.random((kr, kc), dtype=np.float32)
+    sc[rng.random((kr, kc)) < 0.05] = 0.5            # ties
+    sc[0, :7] = np.nan
+    sc[1, :3] = -np.inf
+    got = S.siting_findmax(torch.from_numpy(sc).cuda(), torch.from_numpy(z).cuda(), 9, 8, 20,
+                           key_stride=stride).cpu().numpy()
+    assert (got == orc.findmax(sc, z, 9, 8, 20, stride=stride)).all()
+
+
+# ----------------------------------------------------------- VIEWSHED ------
+def _viewshed_case(S, orc, z, obs, rmax, sched=None):
+    nr, nc = z.shape
+    zd = torch.from_numpy(z).cuda()
+    off = S.siting_viewshed_layout(obs, nr, nc)
+    obs_d = S.observers_to_device(obs)
+    off_d = torch.from_numpy(off).cuda()
+    order_d = torch.from_numpy(S.siting_viewshed_order(obs)).cuda()
+    bm = S.siting_viewshed_batch(zd, obs_d, off_d, rmax, order_dev=order_d, sched=sched)
+    want, woff = orc.viewshed(z, obs)
+    assert (woff == off).all()
+    return _u64(bm)[:off[-1]], want
+
+
+def test_viewshed_plain_1000_candidates(S, orc):
+    # the plain workload: 1000^2, ROI 100, h = 10/10, 1000 candidates
+    z = _terrain(1000, 2.4, 1000, 1)
+    from synth import uniform_observers
+    obs = uniform_observers(1000, 1000, 1000, 5, roi=(100, 100), height=(10, 10))
+    got, want = _viewshed_case(S, orc, z, obs, 100)
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, bad[:10]
+
+
+@pytest.mark.parametrize("seed,roi,height,shape", [
+    (1, (1, 40), (0, 30), (300, 350)),
+    (2, (50, 160), (5, 100), (700, 640)),
+    (3, (150, 300), (0, 200), (650, 701)),
+])
+def test_viewshed_uneven_clipped(S, orc, seed, roi, height, shape):
+    _say("viewshed uneven", seed, roi, shape)
+    from synth import uniform_observers
+    z = _terrain(shape[0], 2.2, 3000, seed, ncols=shape[1])
+    obs = uniform_observers(shape[0], shape[1], 300, seed, roi=roi, height=height)
+    got, want = _viewshed_case(S, orc, z, obs, roi[1])
+    assert (got == want).all()
+
+
+def test_viewshed_every_schedule_same_bits(S, orc):
+    from synth import uniform_observers
+    z = _terrain(500, 2.4, 2000, 8)
+    obs = uniform_observers(500, 500, 200, 8, roi=(30, 120), height=(2, 40))
+    want, _ = orc.viewshed(z, obs)
+    for sc in S.siting_autotune_candidates(120):
+        _say("schedule", sc)
+        got, _ = _viewshed_case(S, orc, z, obs, 120, sched=sc)
+        assert (got == want).all(), sc
+
+
+def test_viewshed_wide_arithmetic(S, orc):
+    # extreme relief forces the int64 comparison path
+    rng = np.random.default_rng(0)
+    z = rng.integers(-32768, 32767, size=(260, 270)).astype(np.int16)
+    from synth import uniform_observers
+    obs = uniform_observers(260, 270, 60, 9, roi=(60, 120), height=(0, 32767))
+    got, want = _viewshed_case(S, orc, z, obs, 120)
+    assert (got == want).all()
+
+
+def test_viewshed_count_sink(S, orc):
+    from synth import uniform_observers
+    z = _terrain(400, 2.4, 1200, 21)
+    obs = uniform_observers(400, 400, 150, 21, roi=(5, 110), height=(0, 50))
+    zd = torch.from_numpy(z).cuda()
+    vis, cells = S.siting_viewshed_batch(zd, S.observers_to_device(obs), None, 110,
+                                         sink=S.SITING_SINK_COUNT)
+    wv, wc = orc.viewshed_count(z, obs)
+    assert (vis.cpu().numpy().astype(np.uint32) == wv).all()
+    assert (cells.cpu().numpy().astype(np.uint32) == wc).all()
+
+
+def test_autotune_returns_a_candidate(S, orc):
+    from synth import uniform_observers
+    z = _terrain(600, 2.4, 1000, 2)
+    obs = uniform_observers(600, 600, 400, 2, roi=(100, 100), height=(10, 10))
+    zd = torch.from_numpy(z).cuda()
+    off = S.siting_viewshed_layout(obs, 600, 600)
+    off_d = torch.from_numpy(off).cuda()
+    obs_d = S.observers_to_device(obs)
+    bm = torch.empty(int(off[-1]), dtype=torch.int64, device="cuda")
+    best, times = S.siting_autotune(zd, obs_d, off_d, 100, bm)
+    assert best.as_tuple() in [c.as_tuple() for c in S.siting_autotune_candidates(100)]
+    assert all(t > 0 for t in times)
+    want, _ = orc.viewshed(z, obs)
+    assert (_u64(bm)[:off[-1]] == want).all()
+
+
+# --------------------------------------------------------------- SITE ------
+@pytest.mark.parametrize("seed,n_obs,max_obs,frac", [(1, 400, 60, 1.0), (2, 300, 1000, 0.5),
+                                                     (3, 50, 200, 1.0)])
+def test_greedy_parity(S, orc, seed, n_obs, max_obs, frac):
+    _say("greedy", seed, n_obs, max_obs, frac)
+    from synth import uniform_observers
+    z = _terrain(500, 2.4, 1500, seed)
+    obs = uniform_observers(500, 500, n_obs, seed, roi=(20, 90), height=(5, 30))
+    bm_h, off = orc.viewshed(z, obs)
+    tgt = 500 * 500 if frac >= 1 else int(math.ceil(frac * 500 * 500))
+    wsel, wgain, wcum, _ = orc.greedy(bm_h, off, obs, 500, 500, max_obs, tgt, lazy=True)
+    bm = torch.from_numpy(bm_h.view(np.int64)).cuda()
+    sel, gains, nsel, cum = S.siting_greedy(bm, torch.from_numpy(off).cuda(),
+                                            S.observers_to_device(obs), 500, 500, max_obs, tgt)
+    m = int(nsel.item())
+    assert m == len(wsel)
+    assert (sel[:m].cpu().numpy() == wsel).all()
+    assert (gains[:m].cpu().numpy() == wgain).all()
+    assert (_u64(cum).reshape(-1) == wcum.reshape(-1)).all()
+
+
+# ------------------------------------------------------------- PIPELINE ----
+def test_pipeline_plain_1000_end_to_end(S, orc):
+    from paper_2006_16783_amd import pipeline as P
+    cfg = P.CONFIGS["plain_1000"]
+    z = _terrain(cfg.n, cfg.beta, cfg.zmax, cfg.seed)
+    zd = torch.from_numpy(z).cuda()
+    res = P.run(zd, cfg)
+    cnt = orc.vix(z, cfg.roi, cfg.h_t, cfg.h_r, cfg.K, cfg.vix_seed)
+    cand = orc.findmax(cnt, z, cfg.grid, cfg.grid, cfg.k)
+    cand = cand[cand >= 0]
+    assert (res.candidates == cand).all()
+    obs = orc.observers(cand % cfg.n, cand // cfg.n, cfg.roi, cfg.h_t, cfg.h_r)
+    bm, off = orc.viewshed(z, obs)
+    sel, gains, cum = orc.greedy(bm, off, obs, cfg.n, cfg.n, cfg.max_obs,
+                                 P.target_cells(cfg.target_frac, cfg.n, cfg.n))
+    assert (res.selected == sel).all() and (res.gains == gains).all()
+    # coverage is non-decreasing and equals the union's popcount
+    assert (np.diff(res.gains) <= 0).all()
+    assert res.coverage_cells == sum(bin(int(v)).count("1") for v in cum.ravel())
