@@ -1,0 +1,265 @@
+#!/usr/bin/env python3
+"""Benchmark of the siting path on one MI355X.
+
+Workload (default): the full-scale configuration -- a 46400 x 46400 int16 fBm
+terrain (2.15e9 posts, exponent 2.4, 0-4000 m) resident in HBM, ROI 100,
+heights 10/10, VIX with 10 receivers per post, FINDMAX on a 64 x 64 block
+grid keeping 20 per block (81,920 candidates), SITE greedy to 4096 observers.
+
+One step = one pass of the whole path: VIX -> FINDMAX -> layout -> VIEWSHED
+(one persistent launch) -> SITE -> selected list on the host.
+
+Printed: ONE JSON line.  `value` is the viewshed throughput in cell-tests/s
+(in-disk in-terrain cells of all candidate viewsheds / viewshed stage time);
+`siting_wall_s` is the whole step's wall time (the second half of the
+metric).  `roofline` describes the dominant kernel of the step (VIX);
+`cpu_baseline` times the oracle on the host cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+# 32-bit integer VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (non-packed)
+PEAK_INT_TOPS = 256 * 64 * 2.4e9 / 1e12
+# integer ALU operations of one line-of-sight step: advance
+# the crossing (add, compare, conditional subtract), two address updates,
+# interpolate (subtract, two multiplies, add), advance the segment (add),
+# compare
+VIX_OPS_PER_LOS_STEP = 11
+# one viewshed ray step: the line-of-sight step work plus the nearest-cell
+# rounding, disk test, horizon slope products and comparisons, bit address
+VIEWSHED_OPS_PER_RAY_STEP = 24
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash(names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2006_16783_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel: str, src_hash: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when absent or taken on different kernel sources."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+        e = d.get(kernel)
+        if not e or e.get("source_hash") != src_hash:
+            return None
+        return float(e["bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def cpu_baseline(z_host, obs, roi, seconds: float):
+    """The oracle's viewshed on a bounded sample of the candidates (cell-tests/s)
+    and its VIX on a few terrain rows (LOS tests/s), on this host's cores."""
+    import numpy as np
+    import oracle
+    from paper_2006_16783_amd.pipeline import disk_cell_counts
+    oracle.build()
+    nr, nc = z_host.shape
+    rng = np.random.default_rng(0)
+    pick = rng.permutation(len(obs))
+    n = 256
+    t_used = 0.0
+    cells = 0
+    done = 0
+    while done < len(obs):
+        sub = obs[pick[done:done + n]]
+        t0 = time.perf_counter()
+        oracle.viewshed(z_host, sub)
+        dt = time.perf_counter() - t0
+        t_used += dt
+        cells += int(disk_cell_counts(sub, nr, nc).sum())
+        done += len(sub)
+        if t_used >= seconds * 0.6:
+            break
+        n = int(min(len(obs) - done, max(n, n * (seconds * 0.6 - t_used) / max(dt, 1e-3))))
+        if n <= 0:
+            break
+    vs_rate = cells / t_used
+    # VIX: whole rows until ~40% of the budget
+    rows = 1
+    t_vix, tests = 0.0, 0
+    r0 = nr // 2
+    while t_vix < seconds * 0.4:
+        t0 = time.perf_counter()
+        oracle.vix(z_host, roi, 10, 10, 10, 12345, rows=(r0, r0 + rows))
+        t_vix += time.perf_counter() - t0
+        tests += rows * nc * 10
+        r0 += rows
+        rows *= 2
+        if r0 + rows > nr:
+            break
+    return {
+        "value": vs_rate, "unit": "cell-tests/s", "cores": oracle.num_threads(), "kind": "oracle",
+        "sample": f"oracle viewsheds of {done} of the {len(obs)} candidates ({cells} cell-tests, "
+                  f"{t_used:.1f} s); oracle VIX on {tests // (10 * nc)} full rows "
+                  f"({tests} LOS tests, {t_vix:.1f} s)",
+        "vix_los_tests_per_s": tests / t_vix if t_vix > 0 else None,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="full_46400")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the viewshed schedule with the autotuner before timing")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one 1 GiB device copy (counter calibration for rocprof)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the siting path runs on a single device)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2006_16783_amd as S
+    from paper_2006_16783_amd import pipeline as P
+    from synth import fbm_torch
+
+    cfg = P.CONFIGS[args.config]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log(f"[bench] generating {cfg.n}x{cfg.n} fBm terrain on the device")
+    t0 = time.perf_counter()
+    z = fbm_torch(cfg.n, cfg.beta, cfg.zmax, cfg.seed, device=dev)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    log(f"[bench] terrain ready in {gen_s:.1f} s; z range {int(z.min())}..{int(z.max())}")
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    sched = None
+    if args.autotune:
+        # tune on the real candidate set of one pass
+        res0 = P.run(z, cfg, timing=False)
+        obs_d = S.observers_to_device(res0.observers)
+        off_d = torch.from_numpy(res0.offsets).to(dev)
+        bm = torch.empty(int(res0.offsets[-1]), dtype=torch.int64, device=dev)
+        sched, times = S.siting_autotune(z, obs_d, off_d, cfg.roi, bm)
+        log(f"[bench] autotuned schedule {sched}: {['%.2f' % t for t in times]} ms")
+        del bm
+
+    for i in range(args.warmup):
+        r = P.run(z, cfg, sched=sched)
+        log(f"[bench] warmup {i}: {r.stage_ms}")
+    torch.cuda.synchronize()
+    stage_tot = {}
+    results = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        r = P.run(z, cfg, sched=sched)
+        results.append(r)
+        for k, v in r.stage_ms.items():
+            stage_tot[k] = stage_tot.get(k, 0.0) + v
+        log(f"[bench] step {i}: {r.stage_ms}")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    stage_ms = {k: v / args.steps for k, v in stage_tot.items()}
+    last = results[-1]
+    nr, nc = z.shape
+    cells = int(P.disk_cell_counts(last.observers, nr, nc).sum())
+    value = cells / (stage_ms["viewshed"] / 1e3)
+
+    # dominant kernel: VIX.  Exact executed line-of-sight steps from the
+    # counting variant (untimed), ALU ops per step as stated above.
+    _, los_steps, los_tests = S.siting_vix_stats(z, cfg.roi, cfg.h_t, cfg.h_r, cfg.K,
+                                                 cfg.vix_seed)
+    vix_s = stage_ms["vix"] / 1e3
+    achieved = los_steps * VIX_OPS_PER_LOS_STEP / vix_s / 1e12
+    vix_hash = source_hash(["vix.hip", "common.hpp"])
+    roofline = {
+        "bound": "alu", "kernel": "vix_kernel", "achieved": achieved, "peak": PEAK_INT_TOPS,
+        "unit": "Top/s", "frac": achieved / PEAK_INT_TOPS,
+        "traffic": traffic_from_profiles("vix_kernel", vix_hash),
+        "units_per_launch": {"los_steps": los_steps, "los_tests": los_tests,
+                             "ops_per_los_step": VIX_OPS_PER_LOS_STEP},
+        "kernel_ms": stage_ms["vix"],
+        "hbm_frac": (nr * nc * 3) / vix_s / 1e9 / PEAK_HBM_GBS,
+    }
+    ray_steps = int(P.ray_step_counts(last.observers, nr, nc).sum())
+    vs_s = stage_ms["viewshed"] / 1e3
+    vs_ach = ray_steps * VIEWSHED_OPS_PER_RAY_STEP / vs_s / 1e12
+    vs_hash = source_hash(["viewshed.hip", "common.hpp"])
+    bm_bytes = int(last.offsets[-1]) * 8
+    vs_roof = {
+        "bound": "alu", "kernel": "viewshed_kernel", "achieved": vs_ach, "peak": PEAK_INT_TOPS,
+        "unit": "Top/s", "frac": vs_ach / PEAK_INT_TOPS,
+        "traffic": traffic_from_profiles("viewshed_kernel", vs_hash),
+        "units_per_launch": {"ray_steps": ray_steps, "cell_tests": cells,
+                             "ops_per_ray_step": VIEWSHED_OPS_PER_RAY_STEP},
+        "kernel_ms": stage_ms["viewshed"],
+        "hbm_frac": (cells * 2 + bm_bytes) / vs_s / 1e9 / PEAK_HBM_GBS,
+    }
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the oracle on the host (bounded sample)")
+        z_host = z.cpu().numpy()
+        cpu = cpu_baseline(z_host, last.observers, cfg.roi, args.cpu_seconds)
+        del z_host
+
+    out = {
+        "metric": "viewshed cell-tests/s; siting wall-time at 46400², 4096 observers",
+        "value": value,
+        "unit": "cell-tests/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "siting_wall_s": ms_per_step / 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: {cfg.n}x{cfg.n} int16 fBm terrain (beta {cfg.beta}, "
+                               f"0-{cfg.zmax} m), ROI {cfg.roi}, h {cfg.h_t}/{cfg.h_r}, VIX K={cfg.K}, "
+                               f"FINDMAX {cfg.grid}x{cfg.grid} x {cfg.k}, SITE to {cfg.max_obs}",
+                   "candidates": int(len(last.observers)), "selected": int(len(last.selected)),
+                   "coverage_frac": last.coverage_cells / (nr * nc), "cell_tests": cells,
+                   "parallelism": "single GPU"},
+        "stage_ms": stage_ms,
+        "terrain_gen_s": gen_s,
+        "schedule": None if sched is None else sched.as_tuple(),
+        "roofline": roofline,
+        "viewshed_roofline": vs_roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -104,6 +104,15 @@ int siting_vix(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
                int32_t roi, int32_t h_t, int32_t h_r, int32_t K, uint64_t seed,
                uint8_t *count, void *stream);
 
+/* The same computation as siting_vix (identical count output), in a
+ * counting variant for measurement: stats (device, uint64[2]) receives the
+ * number of line-of-sight steps executed (grid-line samples tested, up to and
+ * including the first blocking one) and the number of line-of-sight tests.
+ * Slower than siting_vix; not meant for production runs. */
+int siting_vix_stats(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
+                     int32_t roi, int32_t h_t, int32_t h_r, int32_t K, uint64_t seed,
+                     uint8_t *count, uint64_t *stats, void *stream);
+
 /* ------------------------------------------------------------ FINDMAX ----
  * Spatially spread candidates (stage Findmax): the terrain is split into a
  * grid_r x grid_c grid of blocks, block (bi,bj) spanning rows

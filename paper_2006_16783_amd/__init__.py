@@ -8,7 +8,7 @@ no CPU fallback.
 from . import _lib
 from ._lib import (SitingError, Schedule, OBSERVER_DTYPE, SITING_KEY_U8, SITING_KEY_F32,
                    SITING_SINK_BITMAP, SITING_SINK_COUNT, siting_abi_version, siting_device_cus,
-                   siting_vix, siting_findmax, siting_viewshed_layout, siting_viewshed_order,
+                   siting_vix, siting_vix_stats, siting_findmax, siting_viewshed_layout, siting_viewshed_order,
                    siting_viewshed_workspace_size, siting_viewshed_default_schedule,
                    siting_viewshed_batch, siting_autotune, siting_autotune_candidates,
                    siting_greedy_workspace_size, siting_greedy, observers_to_device)

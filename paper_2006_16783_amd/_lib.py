@@ -57,6 +57,7 @@ def _load():
         "siting_last_error": ([], C.c_char_p),
         "siting_device_cus": ([P], C.c_int),
         "siting_vix": ([P, i64, i64, i64, i32, i32, i32, i32, u64, P, P], C.c_int),
+        "siting_vix_stats": ([P, i64, i64, i64, i32, i32, i32, i32, u64, P, P, P], C.c_int),
         "siting_findmax": ([P, i32, i32, P, i64, i64, i64, i32, i32, i32, P, P], C.c_int),
         "siting_viewshed_layout": ([P, i64, i64, i64, P], i64),
         "siting_viewshed_order": ([P, i64, P], C.c_int),
@@ -138,6 +139,20 @@ def siting_vix(z, roi, h_t, h_r, K, seed, count=None, stream=None):
                                          int(K), C.c_uint64(int(seed) & (2**64 - 1)),
                                          _ptr(count), _stream(stream)))
     return count
+
+
+def siting_vix_stats(z, roi, h_t, h_r, K, seed, count=None, stream=None):
+    """Counting variant of siting_vix: returns (count, los_steps, los_tests)."""
+    import torch
+    nr, nc, ld = _dev_terrain(z)
+    if count is None:
+        count = torch.empty((nr, nc), dtype=torch.uint8, device=z.device)
+    stats = torch.zeros(2, dtype=torch.int64, device=z.device)
+    _check("siting_vix_stats", _lib.siting_vix_stats(
+        _ptr(z), nr, nc, ld, int(roi), int(h_t), int(h_r), int(K),
+        C.c_uint64(int(seed) & (2**64 - 1)), _ptr(count), _ptr(stats), _stream(stream)))
+    st = stats.cpu().tolist()
+    return count, int(st[0]), int(st[1])
 
 
 def siting_findmax(key, z, grid_r, grid_c, k, key_stride=1, cand=None, stream=None):

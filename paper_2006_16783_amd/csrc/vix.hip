@@ -58,8 +58,8 @@ struct GlobalTerrain {
 
 // One line-of-sight test.  `acc.at(0)` is the observer post; target at
 // (dx, dy).  Returns 1 if the receiver is visible.
-template <class Acc>
-__device__ __forceinline__ int los(const Acc &acc, int dx, int dy, int E, int Zt)
+template <bool kCount, class Acc>
+__device__ __forceinline__ int los(const Acc &acc, int dx, int dy, int E, int Zt, uint64_t &steps)
 {
     int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
     int rs = acc.row_stride();
@@ -73,6 +73,8 @@ __device__ __forceinline__ int los(const Acc &acc, int dx, int dy, int E, int Zt
     int dz = Zt - E;
     int r = 0, off = 0;
     for (int k = 1; k < n; k++) {
+        if (kCount)
+            steps++;
         r += mn;
         off += s_maj;
         if (r >= n) {
@@ -89,12 +91,13 @@ __device__ __forceinline__ int los(const Acc &acc, int dx, int dy, int E, int Zt
     return 1;
 }
 
-template <bool kLds>
+template <bool kLds, bool kCount>
 __global__ __launch_bounds__(kVixThreads) void vix_kernel(
     const int16_t *__restrict__ z, int64_t nrows, int64_t ncols, int64_t ld, int R, int h_t,
     int h_r, int K, uint64_t seed, uint8_t *__restrict__ count, int T, int64_t tiles_r,
-    int64_t tiles_c, int64_t per_xcd)
+    int64_t tiles_c, int64_t per_xcd, unsigned long long *__restrict__ stats)
 {
+    uint64_t steps = 0, tests = 0;
     extern __shared__ int16_t tile[];
     // XCD-aware tile order: workgroup b runs on XCD b % 8; give each XCD a
     // contiguous band of tiles.
@@ -161,16 +164,30 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
             }
             if (!ok)
                 continue;
+            if (kCount)
+                tests++;
             if (kLds) {
                 int Zt = la.at(dy * pitch + dx) + h_r;
-                cnt += los(la, dx, dy, E, Zt);
+                cnt += los<kCount>(la, dx, dy, E, Zt, steps);
             } else {
                 int Zt = ga.at((int)(dy * ld + dx)) + h_r;
-                cnt += los(ga, dx, dy, E, Zt);
+                cnt += los<kCount>(ga, dx, dy, E, Zt, steps);
             }
         }
         count[t] = (uint8_t)cnt;
     }
+    if (kCount) {
+        // per-lane totals; the one global atomic per lane is negligible next
+        // to the line-of-sight work and only runs in this counting variant
+        atomicAdd(&stats[0], (unsigned long long)steps);
+        atomicAdd(&stats[1], (unsigned long long)tests);
+    }
+}
+
+__global__ void vix_stats_reset(unsigned long long *stats)
+{
+    stats[0] = 0;
+    stats[1] = 0;
 }
 
 }  // namespace
@@ -178,21 +195,20 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
 
 using namespace siting;
 
-extern "C" int siting_vix(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld, int32_t roi,
-                          int32_t h_t, int32_t h_r, int32_t K, uint64_t seed, uint8_t *count,
-                          void *stream)
+static int vix_launch(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld, int32_t roi,
+                      int32_t h_t, int32_t h_r, int32_t K, uint64_t seed, uint8_t *count,
+                      unsigned long long *stats, void *stream, const char *fn)
 {
-    clear_error();
-    SITING_REQUIRE(z != nullptr && count != nullptr, "siting_vix: NULL terrain or output");
-    SITING_REQUIRE(nrows >= 2 && ncols >= 2, "siting_vix: terrain must be at least 2x2");
-    SITING_REQUIRE(ld >= ncols, "siting_vix: ld (%lld) < ncols (%lld)", (long long)ld,
+    SITING_REQUIRE(z != nullptr && count != nullptr, "%s: NULL terrain or output", fn);
+    SITING_REQUIRE(nrows >= 2 && ncols >= 2, "%s: terrain must be at least 2x2", fn);
+    SITING_REQUIRE(ld >= ncols, "%s: ld (%lld) < ncols (%lld)", fn, (long long)ld,
                    (long long)ncols);
-    SITING_REQUIRE(roi >= 1 && roi <= kMaxRoi, "siting_vix: roi %d outside 1..%d", roi, kMaxRoi);
+    SITING_REQUIRE(roi >= 1 && roi <= kMaxRoi, "%s: roi %d outside 1..%d", fn, roi, kMaxRoi);
     SITING_REQUIRE(h_t >= 0 && h_t <= kMaxHeight && h_r >= 0 && h_r <= kMaxHeight,
-                   "siting_vix: heights outside 0..%d", kMaxHeight);
-    SITING_REQUIRE(K >= 1 && K <= 255, "siting_vix: K %d outside 1..255", K);
+                   "%s: heights outside 0..%d", fn, kMaxHeight);
+    SITING_REQUIRE(K >= 1 && K <= 255, "%s: K %d outside 1..255", fn, K);
     if ((int64_t)(roi + 1) * ld >= ((int64_t)1 << 31)) {
-        set_error("siting_vix: roi*ld too large for 32-bit offsets");
+        set_error("%s: roi*ld too large for 32-bit offsets", fn);
         return SITING_E_UNSUPPORTED;
     }
     // Largest tile side (multiple of 8, <= 128) whose haloed tile fits in LDS.
@@ -213,19 +229,48 @@ extern "C" int siting_vix(const int16_t *z, int64_t nrows, int64_t ncols, int64_
     int64_t per_xcd = (ntiles + 7) / 8;
     int64_t grid = per_xcd * 8;
     if (grid > INT32_MAX) {
-        set_error("siting_vix: terrain too large");
+        set_error("%s: terrain too large", fn);
         return SITING_E_UNSUPPORTED;
     }
     size_t lds = use_lds ? (size_t)(T + 2 * roi) * (T + 2 * roi) * 2 : 0;
     hipStream_t s = as_stream(stream);
-    if (use_lds) {
-        hipLaunchKernelGGL(vix_kernel<true>, dim3((unsigned)grid), dim3(kVixThreads), lds, s, z,
-                           nrows, ncols, ld, roi, h_t, h_r, K, seed, count, T, tiles_r, tiles_c,
-                           per_xcd);
-    } else {
-        hipLaunchKernelGGL(vix_kernel<false>, dim3((unsigned)grid), dim3(kVixThreads), 0, s, z,
-                           nrows, ncols, ld, roi, h_t, h_r, K, seed, count, T, tiles_r, tiles_c,
-                           per_xcd);
+    if (stats) {
+        hipLaunchKernelGGL(vix_stats_reset, dim3(1), dim3(1), 0, s, stats);
+        int rc = check_launch("vix_stats_reset");
+        if (rc != SITING_OK)
+            return rc;
     }
+#define VIX_LAUNCH(LDS, CNT)                                                                    \
+    hipLaunchKernelGGL((vix_kernel<LDS, CNT>), dim3((unsigned)grid), dim3(kVixThreads),        \
+                       LDS ? lds : 0, s, z, nrows, ncols, ld, roi, h_t, h_r, K, seed, count, T, \
+                       tiles_r, tiles_c, per_xcd, stats)
+    if (use_lds && stats)
+        VIX_LAUNCH(true, true);
+    else if (use_lds)
+        VIX_LAUNCH(true, false);
+    else if (stats)
+        VIX_LAUNCH(false, true);
+    else
+        VIX_LAUNCH(false, false);
+#undef VIX_LAUNCH
     return check_launch("vix_kernel");
+}
+
+extern "C" int siting_vix(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld, int32_t roi,
+                          int32_t h_t, int32_t h_r, int32_t K, uint64_t seed, uint8_t *count,
+                          void *stream)
+{
+    clear_error();
+    return vix_launch(z, nrows, ncols, ld, roi, h_t, h_r, K, seed, count, nullptr, stream,
+                      "siting_vix");
+}
+
+extern "C" int siting_vix_stats(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
+                                int32_t roi, int32_t h_t, int32_t h_r, int32_t K, uint64_t seed,
+                                uint8_t *count, uint64_t *stats, void *stream)
+{
+    clear_error();
+    SITING_REQUIRE(stats != nullptr, "siting_vix_stats: NULL stats");
+    return vix_launch(z, nrows, ncols, ld, roi, h_t, h_r, K, seed, count,
+                      reinterpret_cast<unsigned long long *>(stats), stream, "siting_vix_stats");
 }

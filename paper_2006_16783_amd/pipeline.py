@@ -93,6 +93,45 @@ def disk_cell_counts(obs: np.ndarray, nrows: int, ncols: int) -> np.ndarray:
     return out
 
 
+_QUAD_STEPS: dict = {}
+
+
+def _quadrant_ray_steps(eu: int, ev: int, R: int) -> int:
+    """Ray steps that test a cell in one quadrant of a window (rays to the
+    far sides u = eu and v = ev; each ray stops when its nearest cell leaves
+    the ROI disk).  Geometry only, independent of the terrain."""
+    key = (eu, ev, R)
+    if key in _QUAD_STEPS:
+        return _QUAD_STEPS[key]
+    if eu < 1:
+        _QUAD_STEPS[key] = 0
+        return 0
+    rho = np.arange(eu + ev)
+    du = np.where(rho <= ev, eu, eu - (rho - ev))
+    dv = np.where(rho <= ev, rho, ev)
+    n = np.maximum(du, dv).astype(np.int64)
+    mn = np.minimum(du, dv).astype(np.int64)
+    k = np.arange(1, int(n.max()) + 1, dtype=np.int64)[None, :]
+    m = (2 * k * mn[:, None] + n[:, None]) // (2 * n[:, None])
+    ok = (k <= n[:, None]) & (k * k + m * m <= R * R)
+    tot = int(np.cumprod(ok, axis=1).sum())
+    _QUAD_STEPS[key] = tot
+    return tot
+
+
+def ray_step_counts(obs: np.ndarray, nrows: int, ncols: int) -> np.ndarray:
+    """Algorithmic ray steps of each observer's viewshed sweep (the unit of
+    the viewshed kernel's roofline)."""
+    out = np.zeros(len(obs), np.int64)
+    for i, o in enumerate(obs):
+        x, y, R = int(o["x"]), int(o["y"]), int(o["roi"])
+        ex_p, ex_m = min(ncols - 1, x + R) - x, x - max(0, x - R)
+        ey_p, ey_m = min(nrows - 1, y + R) - y, y - max(0, y - R)
+        out[i] = (_quadrant_ray_steps(ex_p, ey_p, R) + _quadrant_ray_steps(ey_p, ex_m, R) +
+                  _quadrant_ray_steps(ex_m, ey_m, R) + _quadrant_ray_steps(ey_m, ex_p, R))
+    return out
+
+
 class _Timer:
     def __init__(self, enabled=True):
         import torch
