@@ -21,7 +21,7 @@
  *    (tangency is visible);
  *  - VIX targets are uniform over the lattice cells of the ROI disk that lie
  *    inside the terrain, drawn by rejection from the terrain-clipped bounding
- *    box with a counter-based Philox4x64-10 stream;
+ *    box with one counter-based Philox4x64-10 stream per post;
  *  - FINDMAX blocks are a G_r x G_c grid with floor(i*N/G) boundaries, ranked
  *    by (count desc, elevation desc, linear index asc);
  *  - the viewshed sweeps rays from the observer to every boundary cell of the
@@ -127,38 +127,53 @@ int or_los(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
  * for every post, K receivers drawn uniformly from the ROI disk, each tested
  * for line of sight; the output is the number of visible receivers.
  *
- * Draw j of post t (t = y*ncols + x) uses attempts a = 0,1,...,63.  Attempt a
- * takes word (a mod 4) of Philox4x64-10(counter = {t, j, a/4, 0},
- * key = {seed, 0}).  With the terrain-clipped box [bx0,bx1] x [by0,by1]
- * around the post, the candidate is
+ * Post t (t = y*ncols + x) owns one stream of 64-bit words: word a is word
+ * (a mod 4) of Philox4x64-10(counter = {t, a/4, 0, 0}, key = {seed, 0}).  The
+ * draws take words in order.  With the terrain-clipped box [bx0,bx1] x
+ * [by0,by1] around the post, a word u proposes
  *     px = bx0 + ((u >> 32) * (bx1-bx0+1)) >> 32,
  *     py = by0 + ((u & 0xffffffff) * (by1-by0+1)) >> 32,
- * accepted iff (px,py) != (x,y) and (px-x)^2 + (py-y)^2 <= R^2.  A draw with
- * no accepted attempt among the 64 counts as not visible.
- * If vtx/vty are non-NULL they receive the accepted targets of post (x0d,y0d)
- * (-1 when none), for test dumps.                                          */
+ * accepted iff (px,py) != (x,y) and (px-x)^2 + (py-y)^2 <= R^2.  Draw j is
+ * the next accepted proposal; after 64 consecutive rejections draw j fails
+ * (counts as not visible) and draw j+1 continues with the following word.
+ * The K targets of post (x,y) can be dumped with or_vix_targets.           */
 #define OR_VIX_MAX_ATTEMPTS 64
 
-static int vix_draw(int64_t nrows, int64_t ncols, int64_t x, int64_t y, int32_t R,
-                    uint64_t seed, int32_t j, int64_t *ox, int64_t *oy)
-{
-    int64_t t = y * ncols + x;
-    int64_t bx0 = x - R < 0 ? 0 : x - R;
-    int64_t bx1 = x + R > ncols - 1 ? ncols - 1 : x + R;
-    int64_t by0 = y - R < 0 ? 0 : y - R;
-    int64_t by1 = y + R > nrows - 1 ? nrows - 1 : y + R;
-    uint64_t wx = (uint64_t)(bx1 - bx0 + 1), wy = (uint64_t)(by1 - by0 + 1);
-    uint64_t key[2] = {seed, 0};
+typedef struct {
+    int64_t t, x, y, bx0, by0;
+    uint64_t wx, wy, seed;
+    uint64_t a;          /* next word of the stream */
     uint64_t blk[4];
-    for (int a = 0; a < OR_VIX_MAX_ATTEMPTS; a++) {
-        if ((a & 3) == 0) {
-            uint64_t ctr[4] = {(uint64_t)t, (uint64_t)j, (uint64_t)(a >> 2), 0};
-            or_philox4x64_10(ctr, key, blk);
+} vix_stream;
+
+static void vix_stream_init(vix_stream *s, int64_t nrows, int64_t ncols, int64_t x, int64_t y,
+                            int32_t R, uint64_t seed)
+{
+    s->t = y * ncols + x;
+    s->x = x; s->y = y;
+    s->bx0 = x - R < 0 ? 0 : x - R;
+    int64_t bx1 = x + R > ncols - 1 ? ncols - 1 : x + R;
+    s->by0 = y - R < 0 ? 0 : y - R;
+    int64_t by1 = y + R > nrows - 1 ? nrows - 1 : y + R;
+    s->wx = (uint64_t)(bx1 - s->bx0 + 1);
+    s->wy = (uint64_t)(by1 - s->by0 + 1);
+    s->seed = seed;
+    s->a = 0;
+}
+
+static int vix_draw(vix_stream *s, int32_t R, int64_t *ox, int64_t *oy)
+{
+    uint64_t key[2] = {s->seed, 0};
+    for (int att = 0; att < OR_VIX_MAX_ATTEMPTS; att++) {
+        if ((s->a & 3) == 0) {
+            uint64_t ctr[4] = {(uint64_t)s->t, s->a >> 2, 0, 0};
+            or_philox4x64_10(ctr, key, s->blk);
         }
-        uint64_t u = blk[a & 3];
-        int64_t px = bx0 + (int64_t)(((u >> 32) * wx) >> 32);
-        int64_t py = by0 + (int64_t)(((u & 0xffffffffULL) * wy) >> 32);
-        int64_t ddx = px - x, ddy = py - y;
+        uint64_t u = s->blk[s->a & 3];
+        s->a++;
+        int64_t px = s->bx0 + (int64_t)(((u >> 32) * s->wx) >> 32);
+        int64_t py = s->by0 + (int64_t)(((u & 0xffffffffULL) * s->wy) >> 32);
+        int64_t ddx = px - s->x, ddy = py - s->y;
         if ((ddx != 0 || ddy != 0) && ddx * ddx + ddy * ddy <= (int64_t)R * R) {
             *ox = px; *oy = py;
             return 1;
@@ -177,9 +192,11 @@ void or_vix(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
     for (int64_t y = row0; y < row1; y++) {
         for (int64_t x = 0; x < ncols; x++) {
             int c = 0;
+            vix_stream st;
+            vix_stream_init(&st, nrows, ncols, x, y, R, seed);
             for (int32_t j = 0; j < K; j++) {
                 int64_t px, py;
-                if (vix_draw(nrows, ncols, x, y, R, seed, j, &px, &py))
+                if (vix_draw(&st, R, &px, &py))
                     c += or_los(z, nrows, ncols, ld, x, y, px, py, h_t, h_r);
             }
             count[y * ncols + x] = (uint8_t)c;
@@ -191,9 +208,11 @@ void or_vix(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
 void or_vix_targets(int64_t nrows, int64_t ncols, int64_t x, int64_t y, int32_t R,
                     int32_t K, uint64_t seed, int64_t *tx, int64_t *ty)
 {
+    vix_stream st;
+    vix_stream_init(&st, nrows, ncols, x, y, R, seed);
     for (int32_t j = 0; j < K; j++) {
         int64_t px = -1, py = -1;
-        vix_draw(nrows, ncols, x, y, R, seed, j, &px, &py);
+        vix_draw(&st, R, &px, &py);
         tx[j] = px; ty[j] = py;
     }
 }

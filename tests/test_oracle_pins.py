@@ -120,27 +120,30 @@ def test_vix_targets_valid_and_counted(orc):
 
 
 def test_vix_draw_formula_from_numpy_philox(orc):
-    # the first accepted attempt of draw j is word (a mod 4) of the Philox
-    # block {t, j, a//4, 0} keyed {seed, 0}, mapped into the clipped box.
+    # post t's words: word a = word (a mod 4) of the Philox block {t, a//4, 0, 0}
+    # keyed {seed, 0}; draws take the accepted proposals in order, a draw
+    # giving up after 64 consecutive rejections.
     nr, nc, R, seed = 50, 60, 7, 1234
     for (x, y) in [(0, 0), (30, 20), (59, 49), (3, 45)]:
-        tx, ty = orc.vix_targets(nr, nc, x, y, R, 5, seed)
+        tx, ty = orc.vix_targets(nr, nc, x, y, R, 9, seed)
         t = y * nc + x
         bx0, bx1 = max(0, x - R), min(nc - 1, x + R)
         by0, by1 = max(0, y - R), min(nr - 1, y + R)
-        for j in range(5):
-            a = 0
+        # numpy's Philox increments its counter before each block
+        words = []
+        for b in range(40):
+            bg = np.random.Philox(key=np.array([seed, 0], np.uint64),
+                                  counter=np.array(_dec256([t, b, 0, 0]), np.uint64))
+            words += [int(w) for w in bg.random_raw(4)]
+        a = 0
+        for j in range(9):
             while True:
-                if a % 4 == 0:
-                    prev = _dec256([t, j, a // 4, 0])
-                    blk = np.random.Philox(key=np.array([seed, 0], np.uint64),
-                                           counter=np.array(prev, np.uint64)).random_raw(4)
-                u = int(blk[a % 4])
+                u = words[a]
+                a += 1
                 px = bx0 + (((u >> 32) * (bx1 - bx0 + 1)) >> 32)
                 py = by0 + (((u & 0xffffffff) * (by1 - by0 + 1)) >> 32)
                 if (px, py) != (x, y) and (px - x) ** 2 + (py - y) ** 2 <= R * R:
                     break
-                a += 1
             assert (tx[j], ty[j]) == (px, py)
 
 
