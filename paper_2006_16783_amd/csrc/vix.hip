@@ -1,5 +1,5 @@
 // VIX: estimated visibility index of every post from K random receivers in
-// its ROI disk (stage Vix of the siting process), one lane per post.
+// its ROI disk (stage Vix of the siting process).
 //
 // Layout: the terrain is cut into T x T post tiles; a workgroup stages its
 // tile plus an R-post halo ((T+2R)^2 int16) in LDS when that fits, so every
@@ -7,17 +7,54 @@
 // terrain through L2 and tiles only give spatial locality.  Tiles are handed
 // to XCDs in contiguous bands so that neighbouring halos share an L2.
 //
+// Scheduling: a line of sight ends at its first blocking sample, so test
+// lengths vary from 1 to R steps (7 on average on rough terrain, while the
+// visible ones run to the end).  One test per lane would leave a wavefront
+// waiting for its longest test.  Instead each wavefront takes batches of 64
+// posts; it first draws the receivers of the batch into a queue in LDS, then
+// its lanes pull tests from the queue, and a lane whose test ends takes the
+// next one (ballot + prefix count), so lanes stay busy until the queue drains.
+// Visible results are accumulated per post with LDS atomics.
+//
+// Draws: post t owns one Philox4x64-10 stream (word a = word a%4 of the
+// block {t, a/4, 0, 0} under key {seed, 0}); the generator runs only when some
+// lane of the wavefront has used up its block, with all lanes computing it
+// together.
+//
 // Exactness: everything is integer.  At major step k of a LOS of length n
 // (k*|minor| = q*n + r) the terrain sample is S = z0*n + (z1-z0)*r and the
-// segment is E*n + (Z-E)*k; with |z| < 2^15, n <= 16383 and heights <= 2^15
+// segment is E*n + (Z-E)*k; with |z| < 2^15, n <= 4094 and heights <= 2^15
 // every term fits in int32 and the 24-bit multiplier is exact.
+#include <cstdlib>
+
 #include "common.hpp"
 
 namespace siting {
 namespace {
 
-constexpr int kVixThreads = 1024;
-constexpr int kVixMaxAttempts = 64;
+constexpr int kVixWaves = 8;
+constexpr int kVixThreads = 64 * kVixWaves;
+constexpr int kVixChunk = 10;          // draws per post per queue round
+constexpr int kVixMaxAttempts = 64;    // consecutive rejections before a draw fails
+constexpr int kVixMaxRoi = 4094;       // queue entries hold dx, dy in 13 bits
+constexpr uint32_t kSkip = 0xFFFFFFFFu;
+
+// LDS bytes besides the tile: per wavefront a queue of 64 x kVixChunk tests
+// and per-post offset, eye height and visible count.
+constexpr int kVixWaveLds = 64 * (kVixChunk * 4 + 12);
+
+// Full 128-bit product of two 64-bit words from four 32x32->64 multiply-adds
+// (schoolbook, carries folded into the adds).
+__device__ __forceinline__ void mul128(uint64_t a, uint64_t b, uint64_t &hi, uint64_t &lo)
+{
+    const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+    const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+    const uint64_t t = (uint64_t)a0 * b0;
+    const uint64_t u = (uint64_t)a1 * b0 + (t >> 32);
+    const uint64_t v = (uint64_t)a0 * b1 + (uint32_t)u;
+    hi = (uint64_t)a1 * b1 + (u >> 32) + (v >> 32);
+    lo = (v << 32) | (uint32_t)t;
+}
 
 // Philox4x64-10 block function (Salmon et al., SC'11).
 __device__ __forceinline__ void philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
@@ -27,8 +64,9 @@ __device__ __forceinline__ void philox4x64_10(uint64_t c0, uint64_t c1, uint64_t
     constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
 #pragma unroll
     for (int round = 0; round < 10; round++) {
-        uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
-        uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+        uint64_t hi0, lo0, hi1, lo1;
+        mul128(M0, c0, hi0, lo0);
+        mul128(M1, c2, hi1, lo1);
         uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
         c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
         k0 += W0; k1 += W1;
@@ -36,149 +74,203 @@ __device__ __forceinline__ void philox4x64_10(uint64_t c0, uint64_t c1, uint64_t
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
-// Terrain accessor: LDS tile (int16 in shared memory) or global memory.
-struct LdsTerrain {
-    const int16_t *base;  // LDS tile; (gx, gy) at (gy - oy) * pitch + (gx - ox)
-    int pitch;
-    int64_t ox, oy;
-    __device__ __forceinline__ int offset(int64_t gx, int64_t gy) const
-    {
-        return (int)((gy - oy) * pitch + (gx - ox));
-    }
-    __device__ __forceinline__ int row_stride() const { return pitch; }
-    __device__ __forceinline__ int at(int off) const { return base[off]; }
-};
-
-struct GlobalTerrain {
-    const int16_t *base;  // global terrain; (gx, gy) at gy * ld + gx, relative to the post
-    int64_t ld;
-    __device__ __forceinline__ int row_stride() const { return (int)ld; }
-    __device__ __forceinline__ int at(int off) const { return base[off]; }
-};
-
-// One line-of-sight test.  `acc.at(0)` is the observer post; target at
-// (dx, dy).  Returns 1 if the receiver is visible.
-template <bool kCount, class Acc>
-__device__ __forceinline__ int los(const Acc &acc, int dx, int dy, int E, int Zt, uint64_t &steps)
+// 24-bit signed multiply (full rate).  Operands here are a post elevation
+// (16 bits), a LOS length, step remainder or a tile pitch (< 2^13), so the
+// product is exact; written out because the compiler loses those ranges.
+__device__ __forceinline__ int mul_i24(int a, int b)
 {
-    int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
-    int rs = acc.row_stride();
-    int sx = dx < 0 ? -1 : 1, sy = dy < 0 ? -rs : rs;
-    bool xmaj = adx >= ady;
-    int n = xmaj ? adx : ady, mn = xmaj ? ady : adx;
-    int s_maj = xmaj ? sx : sy, s_min = xmaj ? sy : sx;
-    if (n <= 1)
-        return 1;
-    int rhs = __mul24(E, n);
-    int dz = Zt - E;
-    int r = 0, off = 0;
-    for (int k = 1; k < n; k++) {
-        if (kCount)
-            steps++;
-        r += mn;
-        off += s_maj;
-        if (r >= n) {
-            r -= n;
-            off += s_min;
-        }
-        int z0 = acc.at(off);
-        int z1 = acc.at(off + s_min);  // in the observer-target box for k < n
-        int S = __mul24(z0, n) + __mul24(z1 - z0, r);
-        rhs += dz;
-        if (S > rhs)
-            return 0;
-    }
-    return 1;
+    int r;
+    asm("v_mul_i32_i24 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
 }
 
-template <bool kLds, bool kCount>
+__device__ __forceinline__ uint32_t pack_test(int lane, int dx, int dy)
+{
+    return ((uint32_t)lane << 26) | ((uint32_t)(dx + 4096) << 13) | (uint32_t)(dy + 4096);
+}
+
+// kLds: terrain tile staged in LDS (else global reads).  kCount: also count
+// executed LOS steps and tests.  kSPI: LOS steps per queue iteration.
+template <bool kLds, bool kCount, int kSPI>
 __global__ __launch_bounds__(kVixThreads) void vix_kernel(
     const int16_t *__restrict__ z, int64_t nrows, int64_t ncols, int64_t ld, int R, int h_t,
     int h_r, int K, uint64_t seed, uint8_t *__restrict__ count, int T, int64_t tiles_r,
-    int64_t tiles_c, int64_t per_xcd, unsigned long long *__restrict__ stats)
+    int64_t tiles_c, int64_t per_xcd, int tile_bytes, unsigned long long *__restrict__ stats)
 {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_batch;
     uint64_t steps = 0, tests = 0;
-    extern __shared__ int16_t tile[];
     // XCD-aware tile order: workgroup b runs on XCD b % 8; give each XCD a
     // contiguous band of tiles.
-    int64_t b = blockIdx.x;
-    int64_t t_id = (b & 7) * per_xcd + (b >> 3);
+    const int64_t b = blockIdx.x;
+    const int64_t t_id = (b & 7) * per_xcd + (b >> 3);
     if (t_id >= tiles_r * tiles_c)
         return;
-    int64_t tr = t_id / tiles_c, tc = t_id % tiles_c;
-    int64_t r0 = tr * T, c0 = tc * T;
-    int64_t oy = r0 - R, ox = c0 - R;
-    int pitch = T + 2 * R;
+    const int64_t r0 = (t_id / tiles_c) * T, c0 = (t_id % tiles_c) * T;
+    const int pitch = T + 2 * R;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int16_t *tile = reinterpret_cast<int16_t *>(smem);
+    uint32_t *q = reinterpret_cast<uint32_t *>(smem + tile_bytes) + wave * 64 * kVixChunk;
+    int32_t *pofs = reinterpret_cast<int32_t *>(smem + tile_bytes) +
+                    kVixWaves * 64 * kVixChunk + wave * 64;
+    int32_t *pE = pofs + kVixWaves * 64;
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(pE + kVixWaves * 64);
+    if (tid == 0)
+        s_batch = 0;
     if (kLds) {
-        int64_t gy0 = oy < 0 ? 0 : oy, gy1 = r0 + T + R > nrows ? nrows : r0 + T + R;
-        int64_t gx0 = ox < 0 ? 0 : ox, gx1 = c0 + T + R > ncols ? ncols : c0 + T + R;
-        int w = (int)(gx1 - gx0), h = (int)(gy1 - gy0);
-        int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nwaves = blockDim.x >> 6;
-        for (int row = wave; row < h; row += nwaves) {
+        const int64_t oy = r0 - R, ox = c0 - R;
+        const int64_t gy0 = oy < 0 ? 0 : oy, gy1 = r0 + T + R > nrows ? nrows : r0 + T + R;
+        const int64_t gx0 = ox < 0 ? 0 : ox, gx1 = c0 + T + R > ncols ? ncols : c0 + T + R;
+        const int w = (int)(gx1 - gx0), h = (int)(gy1 - gy0);
+        for (int row = wave; row < h; row += kVixWaves) {
             const int16_t *src = z + (gy0 + row) * ld + gx0;
             int16_t *dst = tile + (gy0 + row - oy) * pitch + (gx0 - ox);
             for (int col = lane; col < w; col += 64)
                 dst[col] = src[col];
         }
-        __syncthreads();
     }
-    int64_t tile_rows = (r0 + T > nrows ? nrows : r0 + T) - r0;
-    int64_t tile_cols = (c0 + T > ncols ? ncols : c0 + T) - c0;
-    int64_t R2 = (int64_t)R * R;
-    for (int p = threadIdx.x; p < T * T; p += blockDim.x) {
-        int py = p / T, px = p % T;
-        if (py >= tile_rows || px >= tile_cols)
-            continue;
-        int64_t y = r0 + py, x = c0 + px;
-        int64_t t = y * ncols + x;
-        int64_t bx0 = x - R < 0 ? 0 : x - R, bx1 = x + R > ncols - 1 ? ncols - 1 : x + R;
-        int64_t by0 = y - R < 0 ? 0 : y - R, by1 = y + R > nrows - 1 ? nrows - 1 : y + R;
-        uint64_t wx = (uint64_t)(bx1 - bx0 + 1), wy = (uint64_t)(by1 - by0 + 1);
-        int E, cnt = 0;
-        LdsTerrain la;
-        GlobalTerrain ga;
-        if (kLds) {
-            la.pitch = pitch; la.ox = ox; la.oy = oy;
-            la.base = tile + la.offset(x, y);
-            E = la.at(0) + h_t;
-        } else {
-            ga.base = z + y * ld + x;
-            ga.ld = ld;
-            E = ga.at(0) + h_t;
-        }
-        for (int j = 0; j < K; j++) {
-            uint64_t blk[4];
-            int dx = 0, dy = 0, ok = 0;
-            for (int a = 0; a < kVixMaxAttempts && !ok; a++) {
-                if ((a & 3) == 0)
-                    philox4x64_10((uint64_t)t, (uint64_t)j, (uint64_t)(a >> 2), 0, seed, 0, blk);
-                uint64_t u = blk[a & 3];
-                int64_t px_ = bx0 + (int64_t)(((u >> 32) * wx) >> 32);
-                int64_t py_ = by0 + (int64_t)(((u & 0xffffffffull) * wy) >> 32);
-                int64_t ddx = px_ - x, ddy = py_ - y;
-                if ((ddx | ddy) != 0 && ddx * ddx + ddy * ddy <= R2) {
-                    ok = 1;
-                    dx = (int)ddx;
-                    dy = (int)ddy;
+    __syncthreads();
+    // terrain base: LDS tile origin (r0-R, c0-R), or the global post (r0, c0)
+    const int16_t *zb = kLds ? tile : z + r0 * ld + c0;
+    const int rs = kLds ? pitch : (int)ld;
+    const int tile_rows = (int)((r0 + T > nrows ? nrows : r0 + T) - r0);
+    const int tile_cols = (int)((c0 + T > ncols ? ncols : c0 + T) - c0);
+    const int R2 = R * R;
+    const int nposts = T * T, nbatch = (nposts + 63) >> 6;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+
+    for (;;) {
+        int bt = 0;
+        if (lane == 0)
+            bt = atomicAdd(&s_batch, 1);
+        bt = __shfl(bt, 0, 64);
+        if (bt >= nbatch)
+            break;
+        const int p = bt * 64 + lane;
+        const int py = p / T, px = p - py * T;
+        const bool valid = p < nposts && py < tile_rows && px < tile_cols;
+        const int64_t y = r0 + py, x = c0 + px;
+        const int po = kLds ? (py + R) * pitch + (px + R) : py * (int)ld + px;
+        const int Epost = valid ? (int)zb[po] + h_t : 0;
+        pofs[lane] = po;
+        pE[lane] = Epost;
+        cnt[lane] = 0;
+        // this post's receiver stream
+        const uint64_t t = (uint64_t)(y * ncols + x);
+        const int64_t bx0 = x - R < 0 ? 0 : x - R, bx1 = x + R > ncols - 1 ? ncols - 1 : x + R;
+        const int64_t by0 = y - R < 0 ? 0 : y - R, by1 = y + R > nrows - 1 ? nrows - 1 : y + R;
+        const uint64_t wx = (uint64_t)(bx1 - bx0 + 1), wy = (uint64_t)(by1 - by0 + 1);
+        uint64_t blk_next = 0, w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+        int nbuf = 0;
+        for (int j0 = 0; j0 < K; j0 += kVixChunk) {
+            const int kc = K - j0 < kVixChunk ? K - j0 : kVixChunk;
+            // ---- draw kc receivers per post into the queue
+            const int need = valid ? kc : 0;
+            int made = 0, att = 0;
+            for (int j = need; j < kc; j++)
+                q[j * 64 + lane] = kSkip;
+            while (__any(made < need)) {
+                const bool want = made < need && nbuf == 0;
+                if (__any(want)) {
+                    uint64_t o[4];
+                    philox4x64_10(t, blk_next, 0, 0, seed, 0, o);
+                    if (want) {
+                        w0 = o[0]; w1 = o[1]; w2 = o[2]; w3 = o[3];
+                        blk_next++;
+                        nbuf = 4;
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    if (made < need && nbuf > 0) {
+                        const uint64_t u = nbuf == 4 ? w0 : nbuf == 3 ? w1 : nbuf == 2 ? w2 : w3;
+                        nbuf--;
+                        att++;
+                        // ((u >> 32) * wx) >> 32, i.e. the high word of a 32x32 product
+                        const int dx = (int)(bx0 - x) + (int)__umulhi((uint32_t)(u >> 32), (uint32_t)wx);
+                        const int dy = (int)(by0 - y) + (int)__umulhi((uint32_t)u, (uint32_t)wy);
+                        const bool ok = (dx | dy) != 0 && dx * dx + dy * dy <= R2;
+                        if (ok || att == kVixMaxAttempts) {
+                            q[made * 64 + lane] = ok ? pack_test(lane, dx, dy) : kSkip;
+                            made++;
+                            att = 0;
+                            if (kCount && ok)
+                                tests++;
+                        }
+                    }
                 }
             }
-            if (!ok)
-                continue;
-            if (kCount)
-                tests++;
-            if (kLds) {
-                int Zt = la.at(dy * pitch + dx) + h_r;
-                cnt += los<kCount>(la, dx, dy, E, Zt, steps);
-            } else {
-                int Zt = ga.at((int)(dy * ld + dx)) + h_r;
-                cnt += los<kCount>(ga, dx, dy, E, Zt, steps);
+            // ---- run the queued tests, refilling idle lanes
+            const int total = kc * 64;
+            int cursor = 0;
+            bool active = false;
+            int n = 0, mn = 0, r = 0, off = 0, smaj = 0, smin = 0, rhs = 0, dz = 0, k = 0, pl = 0;
+            for (;;) {
+                const bool idle = !active;
+                const uint64_t m = __ballot(idle);
+                if (idle) {
+                    const int idx = cursor + __popcll(m & lt_mask);
+                    if (idx < total) {
+                        const uint32_t e = q[idx];
+                        if (e != kSkip) {
+                            pl = (int)(e >> 26);
+                            const int dx = (int)((e >> 13) & 0x1FFF) - 4096;
+                            const int dy = (int)(e & 0x1FFF) - 4096;
+                            const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
+                            const bool xmaj = adx >= ady;
+                            n = xmaj ? adx : ady;
+                            if (n <= 1) {
+                                atomicAdd(&cnt[pl], 1u);  // adjacent: always visible
+                            } else {
+                                const int sx = dx < 0 ? -1 : 1, sy = dy < 0 ? -rs : rs;
+                                mn = xmaj ? ady : adx;
+                                smaj = xmaj ? sx : sy;
+                                smin = xmaj ? sy : sx;
+                                off = pofs[pl];
+                                const int E = pE[pl];
+                                const int Zt = (int)zb[off + (kLds ? mul_i24(dy, rs) : dy * rs) + dx] + h_r;
+                                rhs = E * n;
+                                dz = Zt - E;
+                                r = 0;
+                                k = n - 1;  // steps left
+                                active = true;
+                            }
+                        }
+                    }
+                }
+                cursor += __popcll(m);
+                if (!__any(active) && cursor >= total)
+                    break;
+#pragma unroll
+                for (int sp = 0; sp < kSPI; sp++) {
+                    if (active) {
+                        if (kCount)
+                            steps++;
+                        r += mn;
+                        off += smaj;
+                        if (r >= n) {
+                            r -= n;
+                            off += smin;
+                        }
+                        const int z0 = zb[off];
+                        const int z1 = zb[off + smin];  // in the observer-target box
+                        const int S = mul_i24(z0, n) + mul_i24(z1 - z0, r);
+                        rhs += dz;
+                        k--;
+                        const bool blocked = S > rhs;
+                        if (blocked || k == 0) {
+                            if (!blocked)
+                                atomicAdd(&cnt[pl], 1u);
+                            active = false;
+                        }
+                    }
+                }
             }
         }
-        count[t] = (uint8_t)cnt;
+        if (valid)
+            count[t] = (uint8_t)cnt[lane];
     }
     if (kCount) {
-        // per-lane totals; the one global atomic per lane is negligible next
-        // to the line-of-sight work and only runs in this counting variant
         atomicAdd(&stats[0], (unsigned long long)steps);
         atomicAdd(&stats[1], (unsigned long long)tests);
     }
@@ -211,28 +303,39 @@ static int vix_launch(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld
         set_error("%s: roi*ld too large for 32-bit offsets", fn);
         return SITING_E_UNSUPPORTED;
     }
-    // Largest tile side (multiple of 8, <= 128) whose haloed tile fits in LDS.
-    int lds_max = device_max_lds();
+    if (roi > kVixMaxRoi) {
+        set_error("%s: roi %d above the supported %d", fn, roi, kVixMaxRoi);
+        return SITING_E_UNSUPPORTED;
+    }
+    // Largest tile side (multiple of 8, <= 128) whose haloed tile and the
+    // wavefront queues fit in LDS.
+    const int lds_max = device_max_lds();
+    const int queue_bytes = kVixWaves * kVixWaveLds;
     int T = 0;
     for (int c = 128; c >= 16; c -= 8) {
-        int64_t bytes = (int64_t)(c + 2 * roi) * (c + 2 * roi) * 2;
+        int64_t bytes = (((int64_t)(c + 2 * roi) * (c + 2 * roi) * 2 + 15) & ~15ll) + queue_bytes;
         if (bytes <= lds_max) {
             T = c;
             break;
         }
     }
-    bool use_lds = T > 0;
+    const bool use_lds = T > 0;
     if (!use_lds)
         T = 64;
-    int64_t tiles_r = (nrows + T - 1) / T, tiles_c = (ncols + T - 1) / T;
-    int64_t ntiles = tiles_r * tiles_c;
-    int64_t per_xcd = (ntiles + 7) / 8;
-    int64_t grid = per_xcd * 8;
+    if ((int64_t)(T + 2 * roi + 2) * ld >= ((int64_t)1 << 31)) {
+        set_error("%s: roi*ld too large for 32-bit offsets", fn);
+        return SITING_E_UNSUPPORTED;
+    }
+    const int64_t tiles_r = (nrows + T - 1) / T, tiles_c = (ncols + T - 1) / T;
+    const int64_t ntiles = tiles_r * tiles_c;
+    const int64_t per_xcd = (ntiles + 7) / 8;
+    const int64_t grid = per_xcd * 8;
     if (grid > INT32_MAX) {
         set_error("%s: terrain too large", fn);
         return SITING_E_UNSUPPORTED;
     }
-    size_t lds = use_lds ? (size_t)(T + 2 * roi) * (T + 2 * roi) * 2 : 0;
+    const int tile_bytes = use_lds ? (int)((((int64_t)(T + 2 * roi) * (T + 2 * roi) * 2) + 15) & ~15ll) : 0;
+    const size_t lds = (size_t)tile_bytes + queue_bytes;
     hipStream_t s = as_stream(stream);
     if (stats) {
         hipLaunchKernelGGL(vix_stats_reset, dim3(1), dim3(1), 0, s, stats);
@@ -240,18 +343,33 @@ static int vix_launch(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld
         if (rc != SITING_OK)
             return rc;
     }
-#define VIX_LAUNCH(LDS, CNT)                                                                    \
-    hipLaunchKernelGGL((vix_kernel<LDS, CNT>), dim3((unsigned)grid), dim3(kVixThreads),        \
-                       LDS ? lds : 0, s, z, nrows, ncols, ld, roi, h_t, h_r, K, seed, count, T, \
-                       tiles_r, tiles_c, per_xcd, stats)
+    static const int spi = [] {
+        const char *e = getenv("SITING_VIX_STEPS_PER_ITER");
+        int v = e ? atoi(e) : 4;
+        return v == 1 ? 1 : v == 2 ? 2 : 4;
+    }();
+#define VIX_LAUNCH(LDS, CNT, SPI)                                                              \
+    hipLaunchKernelGGL((vix_kernel<LDS, CNT, SPI>), dim3((unsigned)grid), dim3(kVixThreads),   \
+                       lds, s, z, nrows, ncols, ld, roi, h_t, h_r, K, seed, count, T, tiles_r,  \
+                       tiles_c, per_xcd, tile_bytes, stats)
+#define VIX_SPI(LDS, CNT)                    \
+    do {                                     \
+        if (spi == 1)                        \
+            VIX_LAUNCH(LDS, CNT, 1);         \
+        else if (spi == 2)                   \
+            VIX_LAUNCH(LDS, CNT, 2);         \
+        else                                 \
+            VIX_LAUNCH(LDS, CNT, 4);         \
+    } while (0)
     if (use_lds && stats)
-        VIX_LAUNCH(true, true);
+        VIX_SPI(true, true);
     else if (use_lds)
-        VIX_LAUNCH(true, false);
+        VIX_SPI(true, false);
     else if (stats)
-        VIX_LAUNCH(false, true);
+        VIX_SPI(false, true);
     else
-        VIX_LAUNCH(false, false);
+        VIX_SPI(false, false);
+#undef VIX_SPI
 #undef VIX_LAUNCH
     return check_launch("vix_kernel");
 }
