@@ -121,9 +121,11 @@ int siting_vix_stats(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
  *   key_type SITING_KEY_U8 : key is uint8[nrows*ncols] (a VIX count); rank by
  *            (key desc, z desc, linear index asc); key_stride must be 1.
  *   key_type SITING_KEY_F32: key is float[ceil(nrows/s) * ceil(ncols/s)],
- *            s = key_stride >= 1, scoring post (i*s, j*s); only those posts
- *            are eligible; rank by (key desc, linear index asc); NaN ranks as
- *            -infinity.
+ *            s = key_stride >= 1, one score per s x s cell; a cell belongs
+ *            to the block holding its corner post (i*s, j*s); rank by (key
+ *            desc, cell index asc), NaN as -infinity; a winning cell is
+ *            returned as its highest post (elevation desc, index asc), the
+ *            post siting_cnn_score_terrain scores.
  *   cand   : out (device), int64[grid_r*grid_c*k]: blocks in row-major
  *            order, each with k post indices best first, padded with -1.
  *   1 <= grid_r <= nrows, 1 <= grid_c <= ncols, 1 <= k <= 32.
@@ -230,6 +232,54 @@ int siting_greedy(const uint64_t *bitmaps, const int64_t *offsets, const siting_
                   int64_t n, int64_t nrows, int64_t ncols, int32_t max_obs, int64_t target_cells,
                   uint64_t *cumulative, int64_t *selected, int64_t *gains, int32_t *nselected,
                   void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------ LEARNED RANKING ----
+ * A small CNN predicting a post's visibility index (Definitions: the visible
+ * fraction of the ROI receivers) from the 64 x 64 patch around it, used only
+ * as an alternative FINDMAX key (SITING_KEY_F32); VIEWSHED and SITE stay
+ * exact.  Not part of the paper's method.
+ *   input  P[dy][dx] = bf16(float(z[clamp(cy+dy-32, cx+dx-32)] - z[cy][cx]) * 2^-8)
+ *   conv1 4x4 stride 4, 1->16, ReLU (bf16) -> conv2 3x3 stride 2, 16->16, ReLU
+ *   (bf16) -> conv3 3x3 stride 2, 16->32, ReLU -> mean over 3x3 -> FC 32->1
+ *   -> sigmoid.
+ * Convolutions run on BF16 MFMA with FP32 accumulation.  Parameters are one
+ * fp32 vector of siting_cnn_param_count() values in the order w1[16][4][4],
+ * b1[16], w2[16][3][3][16], b2[16], w3[32][3][3][16], b3[32], wfc[32], bfc.
+ * Posts outside the terrain take the nearest edge post. */
+int siting_cnn_param_count(void);
+
+/* Workspace bytes for a training batch of `batch` posts (activations kept
+ * between siting_cnn_forward and siting_cnn_backward); 0 if batch < 1. */
+size_t siting_cnn_workspace_size(int64_t batch);
+
+/* Training forward pass over the posts centres[0..B) (device int64 linear
+ * indices).  pred (device float[B], may be NULL) receives the predictions;
+ * the activations stay in ws for siting_cnn_backward. */
+int siting_cnn_forward(const float *params, const int16_t *z, int64_t nrows, int64_t ncols,
+                       int64_t ld, const int64_t *centres, int64_t B, float *pred, void *ws,
+                       size_t ws_bytes, void *stream);
+
+/* Gradient of the mean squared error between the predictions of the last
+ * siting_cnn_forward on the same ws and labels[0..B) (device float), written
+ * to grad (device float[param_count]); loss (device float, may be NULL)
+ * receives the loss.  Upstream gradients are rounded to bf16 where they
+ * enter an MFMA; every reduction runs in a fixed order (deterministic). */
+int siting_cnn_backward(const float *params, const float *labels, int64_t B, float *grad,
+                        float *loss, void *ws, size_t ws_bytes, void *stream);
+
+/* One Adam step (Kingma & Ba, bias-corrected; step >= 1) on n fp32 values:
+ * params, first and second moments m, v updated in place. */
+int siting_cnn_adam(float *params, float *m, float *v, const float *grad, int64_t n,
+                    int32_t step, float lr, float beta1, float beta2, float eps, void *stream);
+
+/* Predicted visibility index of every stride x stride cell of the terrain,
+ * evaluated at the cell's highest post (elevation desc, index asc; the post
+ * a SITING_KEY_F32 FINDMAX returns for the cell): score (device float) has
+ * ceil(nrows/stride) x ceil(ncols/stride) entries, row-major.
+ * 1 <= stride <= 64. */
+int siting_cnn_score_terrain(const float *params, const int16_t *z, int64_t nrows,
+                             int64_t ncols, int64_t ld, int32_t stride, float *score,
+                             void *stream);
 
 #ifdef __cplusplus
 }

@@ -51,6 +51,8 @@ def _load():
         lib.or_vix.argtypes = [P, i64, i64, i64, i32, i32, i32, i32, u64, P, i64, i64]
         lib.or_vix_targets.argtypes = [i64, i64, i64, i64, i32, i32, u64, P, P]
         lib.or_findmax.argtypes = [P, i32, i32, P, i64, i64, i64, i32, i32, i32, P]
+        lib.or_cell_max.argtypes = [P, i64, i64, i64, i32, i64, i64]
+        lib.or_cell_max.restype = i64
         lib.or_layout.argtypes = [P, i64, i64, i64, P]
         lib.or_layout.restype = i64
         lib.or_viewshed_one.argtypes = [P, i64, i64, i64, P, P]
@@ -130,7 +132,9 @@ def vix_targets(nrows, ncols, x, y, roi, K, seed):
 
 def findmax(key, z, grid_r, grid_c, k, stride=1) -> np.ndarray:
     """Per-block top-k candidates: stage Findmax.  uint8 keys rank by
-    (key desc, z desc, index asc); float32 keys by (key desc, index asc)."""
+    (key desc, z desc, index asc); float32 keys score the cells of a stride
+    grid, rank by (key desc, cell index asc) and return each cell's highest
+    post."""
     z, nr, nc = _terrain(z)
     key = np.ascontiguousarray(key)
     if key.dtype == np.uint8:
@@ -144,6 +148,16 @@ def findmax(key, z, grid_r, grid_c, k, stride=1) -> np.ndarray:
     _load().or_findmax(_ptr(key), kt, int(stride), _ptr(z), nr, nc, nc, int(grid_r),
                        int(grid_c), int(k), _ptr(out))
     return out
+
+
+def cell_max(z, stride):
+    """Highest post (elevation desc, index asc) of every stride x stride cell,
+    as linear indices, cells in row-major order."""
+    z, nr, nc = _terrain(z)
+    lib = _load()
+    R, C_ = -(-nr // stride), -(-nc // stride)
+    return np.array([lib.or_cell_max(_ptr(z), nr, nc, nc, int(stride), i, j)
+                     for i in range(R) for j in range(C_)], np.int64)
 
 
 def layout(obs, nrows, ncols) -> np.ndarray:

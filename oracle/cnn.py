@@ -6,10 +6,12 @@ it only ranks FINDMAX candidates; VIEWSHED and SITE stay exact.
 TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).  float64 numpy, written
 from the network's definition, sharing nothing with the HIP kernels.
 
-Network (patch of 65 x 65 posts centred on the post):
-  input  P[dy][dx] = bf16( float32(z[clamp(cy+dy-32, cx+dx-32)] - z[cy,cx]) * 1e-3f )
-  conv1  5x5 stride 4, 1 -> 8 channels, ReLU          -> 16 x 16 x 8   (H1, bf16)
-  conv2  3x3 stride 2, 8 -> 16, ReLU                   ->  7 x  7 x 16  (H2, bf16)
+Network (patch of 64 x 64 posts around the post):
+  input  P[dy][dx] = bf16( float32(z[clamp(cy+dy-32, cx+dx-32)] - z[cy,cx]) * 2^-8 ),
+         dy, dx in [0, 64): elevation differences in units of 256 m (the
+         power-of-two scale is exact, so there is one rounding)
+  conv1  4x4 stride 4, 1 -> 16 channels, ReLU         -> 16 x 16 x 16  (H1, bf16)
+  conv2  3x3 stride 2, 16 -> 16, ReLU                  ->  7 x  7 x 16  (H2, bf16)
   conv3  3x3 stride 2, 16 -> 32, ReLU                  ->  3 x  3 x 32  (H3, float)
   global average pool -> 32, fully connected 32 -> 1, sigmoid
 Conv weights are used in bf16, biases and the head in float.  Loss: mean
@@ -20,12 +22,12 @@ from __future__ import annotations
 
 import numpy as np
 
-PATCH = 65
+PATCH = 64
 HALF = 32
 # (name, shape) in the order of the flat parameter vector
 PARAM_SHAPES = [
-    ("w1", (8, 5, 5)), ("b1", (8,)),
-    ("w2", (16, 3, 3, 8)), ("b2", (16,)),
+    ("w1", (16, 4, 4)), ("b1", (16,)),
+    ("w2", (16, 3, 3, 16)), ("b2", (16,)),
     ("w3", (32, 3, 3, 16)), ("b3", (32,)),
     ("wfc", (32,)), ("bfc", (1,)),
 ]
@@ -55,7 +57,7 @@ def bf16(x):
 
 
 def patches(z, centres, round=True):
-    """Input patches (B, 65, 65) for linear post indices `centres`."""
+    """Input patches (B, 64, 64) for linear post indices `centres`."""
     z = np.asarray(z)
     nr, nc = z.shape
     c = np.asarray(centres, np.int64)
@@ -65,8 +67,8 @@ def patches(z, centres, round=True):
     xx = np.clip(cx[:, None] + d[None, :], 0, nc - 1)
     zz = z[yy[:, :, None], xx[:, None, :]].astype(np.int32) - z[cy, cx].astype(np.int32)[:, None, None]
     if round:
-        return bf16(zz.astype(np.float32) * np.float32(1e-3))
-    return zz.astype(np.float64) * 1e-3
+        return bf16(zz.astype(np.float32) * np.float32(2.0 ** -8))
+    return zz.astype(np.float64) * 2.0 ** -8
 
 
 def _conv(x, w, b, stride):
@@ -163,5 +165,4 @@ def init_params(seed=0):
         else:
             fan_in = int(np.prod(shp[1:])) if len(shp) > 1 else shp[0]
             p[name] = rng.standard_normal(shp) * np.sqrt(2.0 / fan_in)
-    p["bfc"] = np.array([-1.0])
     return flatten(p).astype(np.float32).astype(np.float64)

@@ -238,10 +238,27 @@ static int fm_cmp(const void *pa, const void *pb)
 }
 
 /* key_type 0: uint8 keys (VIX counts), one per post; rank (key desc, z desc,
- * index asc).  key_type 1: float keys (surrogate scores) on a lattice of
- * every stride-th post in each direction (key array of ceil(nrows/stride) x
- * ceil(ncols/stride)); only lattice posts are eligible; rank (key desc,
- * index asc), NaN ranked lowest (as -infinity, then by index).            */
+ * index asc).  key_type 1: float keys (surrogate scores) of the cells of a
+ * stride x stride grid (key array of ceil(nrows/stride) x ceil(ncols/stride));
+ * a cell belongs to the block holding its corner post (i*stride, j*stride),
+ * ranks by (key desc, cell index asc) with NaN as -infinity, and stands for
+ * its highest post (elevation desc, index asc), which is the candidate
+ * returned.                                                               */
+int64_t or_cell_max(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld, int32_t stride,
+                    int64_t ci, int64_t cj)
+{
+    int64_t best = -1, bz = 0;
+    for (int64_t y = ci * stride; y < (ci + 1) * stride && y < nrows; y++)
+        for (int64_t x = cj * stride; x < (cj + 1) * stride && x < ncols; x++) {
+            int64_t v = Z(z, ld, x, y);
+            if (best < 0 || v > bz) {
+                best = y * ncols + x;
+                bz = v;
+            }
+        }
+    return best;
+}
+
 void or_findmax(const void *key, int32_t key_type, int32_t stride,
                 const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
                 int32_t grid_r, int32_t grid_c, int32_t k, int64_t *cand)
@@ -271,8 +288,13 @@ void or_findmax(const void *key, int32_t key_type, int32_t stride,
                 items[m++] = it;
             }
         qsort(items, (size_t)m, sizeof(fm_item), fm_cmp);
-        for (int32_t i = 0; i < k; i++)
-            cand[b * k + i] = i < m ? items[i].idx : -1;
+        for (int32_t i = 0; i < k; i++) {
+            int64_t c = i < m ? items[i].idx : -1;
+            if (c >= 0 && key_type == 1)
+                c = or_cell_max(z, nrows, ncols, ld, stride, (c / ncols) / stride,
+                                (c % ncols) / stride);
+            cand[b * k + i] = c;
+        }
         free(items);
     }
 }

@@ -70,6 +70,13 @@ def _load():
         "siting_autotune_candidates": ([i32, P, i32], C.c_int),
         "siting_greedy_workspace_size": ([i64], sz),
         "siting_greedy": ([P, P, P, i64, i64, i64, i32, i64, P, P, P, P, P, sz, P], C.c_int),
+        "siting_cnn_param_count": ([], C.c_int),
+        "siting_cnn_workspace_size": ([i64], sz),
+        "siting_cnn_forward": ([P, P, i64, i64, i64, P, i64, P, P, sz, P], C.c_int),
+        "siting_cnn_backward": ([P, P, i64, P, P, P, sz, P], C.c_int),
+        "siting_cnn_adam": ([P, P, P, P, i64, i32, C.c_float, C.c_float, C.c_float, C.c_float, P],
+                            C.c_int),
+        "siting_cnn_score_terrain": ([P, P, i64, i64, i64, i32, P, P], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -292,3 +299,63 @@ def siting_greedy(bitmaps, offsets_dev, obs_dev, nrows, ncols, max_obs, target_c
         int(target_cells), _ptr(cumulative), _ptr(selected), _ptr(gains), _ptr(nsel), _ptr(ws),
         ws.numel(), _stream(stream)))
     return selected, gains, nsel, cumulative
+
+
+# ---------------------------------------------------------------- CNN ------
+def siting_cnn_param_count() -> int:
+    return int(_lib.siting_cnn_param_count())
+
+
+def siting_cnn_workspace_size(batch: int) -> int:
+    return int(_lib.siting_cnn_workspace_size(int(batch)))
+
+
+def cnn_workspace(batch: int, device="cuda"):
+    import torch
+    return torch.empty(max(siting_cnn_workspace_size(batch), 1), dtype=torch.uint8, device=device)
+
+
+def siting_cnn_forward(params, z, centres, ws, pred=None, stream=None):
+    """Training forward over device int64 centres; returns predictions."""
+    import torch
+    nr, nc, ld = _dev_terrain(z)
+    B = centres.numel()
+    if pred is None:
+        pred = torch.empty(B, dtype=torch.float32, device=z.device)
+    _check("siting_cnn_forward", _lib.siting_cnn_forward(
+        _ptr(params), _ptr(z), nr, nc, ld, _ptr(centres), B, _ptr(pred), _ptr(ws), ws.numel(),
+        _stream(stream)))
+    return pred
+
+
+def siting_cnn_backward(params, labels, ws, grad=None, loss=None, stream=None):
+    """Gradient of the MSE loss for the last forward on ws: (grad, loss)."""
+    import torch
+    B = labels.numel()
+    if grad is None:
+        grad = torch.empty(siting_cnn_param_count(), dtype=torch.float32, device=labels.device)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=labels.device)
+    _check("siting_cnn_backward", _lib.siting_cnn_backward(
+        _ptr(params), _ptr(labels), B, _ptr(grad), _ptr(loss), _ptr(ws), ws.numel(),
+        _stream(stream)))
+    return grad, loss
+
+
+def siting_cnn_adam(params, m, v, grad, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check("siting_cnn_adam", _lib.siting_cnn_adam(
+        _ptr(params), _ptr(m), _ptr(v), _ptr(grad), params.numel(), int(step), float(lr),
+        float(beta1), float(beta2), float(eps), _stream(stream)))
+
+
+def siting_cnn_score_terrain(params, z, stride, score=None, stream=None):
+    """Predicted visibility index on the stride lattice (device float32
+    tensor of ceil(nrows/stride) x ceil(ncols/stride))."""
+    import torch
+    nr, nc, ld = _dev_terrain(z)
+    if score is None:
+        score = torch.empty(((nr + stride - 1) // stride, (nc + stride - 1) // stride),
+                            dtype=torch.float32, device=z.device)
+    _check("siting_cnn_score_terrain", _lib.siting_cnn_score_terrain(
+        _ptr(params), _ptr(z), nr, nc, ld, int(stride), _ptr(score), _stream(stream)))
+    return score

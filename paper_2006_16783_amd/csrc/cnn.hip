@@ -1,0 +1,814 @@
+// Learned ranking: a small CNN that predicts a post's visibility index from
+// the 64 x 64 terrain patch around it, used only as an alternative FINDMAX
+// key.  Forward, backward and Adam are all here; convolutions run on MFMA
+// (v_mfma_f32_16x16x16_bf16: bf16 operands, fp32 accumulation).
+//
+// Network (patch of 64 x 64 posts around the post):
+//   input  P = bf16(float(z[clamped post] - z[centre]) * 2^-8)    64 x 64
+//   conv1  4x4 stride 4, 1 -> 16, ReLU  -> H1 16 x 16 x 16 (bf16)
+//   conv2  3x3 stride 2, 16 -> 16, ReLU -> H2  7 x  7 x 16 (bf16)
+//   conv3  3x3 stride 2, 16 -> 32, ReLU -> H3  3 x  3 x 32 (fp32)
+//   global average pool, fully connected 32 -> 1, sigmoid
+// Parameters are one fp32 vector (w1, b1, w2, b2, w3, b3, wfc, bfc); conv
+// weights are rounded to bf16 where they enter an MFMA.
+//
+// MFMA 16x16x16 operand layout (per lane l of a wavefront): A supplies row
+// l%16, k = 4*(l/16)..+3; B supplies column l%16, k = 4*(l/16)..+3; the
+// accumulator holds column l%16, rows 4*(l/16)..+3.  The 4x4 stride-4 first
+// layer is chosen so that an A fragment is exactly 4 contiguous posts of one
+// patch row (no im2col); conv2/conv3 fragments are 4 contiguous channels of
+// one input position.
+#include <algorithm>
+
+#include "common.hpp"
+
+namespace siting {
+namespace {
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// parameter offsets in the flat fp32 vector
+constexpr int OW1 = 0, OB1 = 256, OW2 = 272, OB2 = 2576, OW3 = 2592, OB3 = 7200, OWFC = 7232,
+              OBFC = 7264, NPARAMS = 7265;
+constexpr int kPatch = 64;
+constexpr int kFwdWaves = 4;
+
+__device__ __forceinline__ short bf16_bits(float f)
+{
+    __bf16 h = (__bf16)f;  // round to nearest even
+    return __builtin_bit_cast(short, h);
+}
+__device__ __forceinline__ float bf16_float(uint16_t b)
+{
+    return __uint_as_float((uint32_t)b << 16);
+}
+__device__ __forceinline__ s4 pack4(float a, float b, float c, float d)
+{
+    s4 r;
+    r.x = bf16_bits(a);
+    r.y = bf16_bits(b);
+    r.z = bf16_bits(c);
+    r.w = bf16_bits(d);
+    return r;
+}
+// Orders this wavefront's LDS writes before its later LDS reads by other
+// lanes of the same wavefront.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ f4 mfma(s4 a, s4 b, f4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// ----------------------------------------------------------------- forward
+// One wavefront per post.  kTrain: posts are given centres and every
+// activation is stored for the backward pass; otherwise the terrain is cut
+// into stride x stride cells, each scored at its highest post, a workgroup
+// shares one staged terrain tile among BL x BL cells, and the prediction is
+// written per cell.
+struct FwdArgs {
+    const float *params;
+    const int16_t *z;
+    int64_t nrows, ncols, ld;
+    // train mode
+    const int64_t *centres;
+    int64_t nposts;
+    uint16_t *Pst, *H1st, *H2st;
+    float *H3st, *gst, *yst;
+    // score mode
+    int stride, BL;
+    int64_t lat_r, lat_c, blocks_c;
+    float *score;
+};
+
+template <bool kTrain>
+__global__ __launch_bounds__(64 * kFwdWaves) void cnn_fwd_kernel(FwdArgs A)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lo = lane & 15, hi = lane >> 4;
+    // per-wave activations: H1 [256 pos][16 ch] bf16, H2 [64 pos][16 ch]
+    uint16_t *H1 = reinterpret_cast<uint16_t *>(smem) + wave * (256 * 16 + 64 * 16);
+    uint16_t *H2 = H1 + 256 * 16;
+    float *tile = reinterpret_cast<float *>(smem + kFwdWaves * (256 * 16 + 64 * 16) * 2);
+
+    // weights as B fragments (bf16) and per-lane biases
+    const float *p = A.params;
+    s4 bw1 = pack4(p[OW1 + lo * 16 + hi * 4 + 0], p[OW1 + lo * 16 + hi * 4 + 1],
+                   p[OW1 + lo * 16 + hi * 4 + 2], p[OW1 + lo * 16 + hi * 4 + 3]);
+    s4 bw2[9], bw3[9][2];
+#pragma unroll
+    for (int t = 0; t < 9; t++) {
+        const float *w = p + OW2 + lo * 144 + t * 16 + hi * 4;
+        bw2[t] = pack4(w[0], w[1], w[2], w[3]);
+#pragma unroll
+        for (int nt = 0; nt < 2; nt++) {
+            const float *u = p + OW3 + (nt * 16 + lo) * 144 + t * 16 + hi * 4;
+            bw3[t][nt] = pack4(u[0], u[1], u[2], u[3]);
+        }
+    }
+    const float b1 = p[OB1 + lo], b2 = p[OB2 + lo];
+    const float b3[2] = {p[OB3 + lo], p[OB3 + 16 + lo]};
+    const float wfc[2] = {p[OWFC + lo], p[OWFC + 16 + lo]};
+    const float bfc = p[OBFC];
+
+    // tile geometry
+    int tw = kPatch, th = kPatch;  // tile width/height in posts
+    int64_t ty0 = 0, tx0 = 0;      // global post of tile (0,0) (unclamped)
+    int nloc = 1;                  // posts handled by this workgroup
+    if (!kTrain) {
+        const int64_t bi = blockIdx.x / A.blocks_c, bj = blockIdx.x % A.blocks_c;
+        // patches are centred on the highest post of each cell: up to
+        // stride-1 posts past the cell corner
+        tw = th = A.BL * A.stride + kPatch - 1;
+        ty0 = bi * A.BL * A.stride - kPatch / 2;
+        tx0 = bj * A.BL * A.stride - kPatch / 2;
+        // stage the clamped tile once for the whole workgroup
+        for (int e = tid; e < th * tw; e += 64 * kFwdWaves) {
+            int r = e / tw, c = e - r * tw;
+            int64_t gy = ty0 + r, gx = tx0 + c;
+            gy = gy < 0 ? 0 : gy > A.nrows - 1 ? A.nrows - 1 : gy;
+            gx = gx < 0 ? 0 : gx > A.ncols - 1 ? A.ncols - 1 : gx;
+            tile[e] = (float)A.z[gy * A.ld + gx];
+        }
+        __syncthreads();
+        nloc = A.BL * A.BL;
+    } else {
+        tile += wave * kPatch * kPatch;
+    }
+
+    const int64_t nwork = kTrain ? A.nposts : nloc;
+    const int64_t step = kTrain ? (int64_t)gridDim.x * kFwdWaves : kFwdWaves;
+    const int64_t first = kTrain ? (int64_t)blockIdx.x * kFwdWaves + wave : wave;
+    for (int64_t w = first; w < nwork; w += step) {
+        // ---- locate the post and its patch origin inside `tile`
+        int64_t pid, cy, cx;
+        int or_ = 0, oc = 0;  // patch origin in the tile
+        if (kTrain) {
+            pid = w;
+            const int64_t c = A.centres[pid];
+            cy = c / A.ncols;
+            cx = c - cy * A.ncols;
+            // stage this post's clamped 64 x 64 window
+            for (int r = 0; r < kPatch; r++) {
+                int64_t gy = cy - kPatch / 2 + r, gx = cx - kPatch / 2 + lane;
+                gy = gy < 0 ? 0 : gy > A.nrows - 1 ? A.nrows - 1 : gy;
+                gx = gx < 0 ? 0 : gx > A.ncols - 1 ? A.ncols - 1 : gx;
+                tile[r * kPatch + lane] = (float)A.z[gy * A.ld + gx];
+            }
+            wave_lds_sync();
+        } else {
+            const int py = (int)(w / A.BL), px = (int)(w % A.BL);
+            const int64_t bi = blockIdx.x / A.blocks_c, bj = blockIdx.x % A.blocks_c;
+            const int64_t li = bi * A.BL + py, lj = bj * A.BL + px;
+            if (li >= A.lat_r || lj >= A.lat_c)
+                continue;
+            pid = li * A.lat_c + lj;
+            // highest post of the cell (elevation desc, index asc): one wave
+            // max over packed (elevation, ~row-major position) keys
+            const int ss = A.stride * A.stride;
+            int best = -1;
+            for (int e = lane; e < ss; e += 64) {
+                const int r = e / A.stride, c = e - r * A.stride;
+                if (li * A.stride + r < A.nrows && lj * A.stride + c < A.ncols) {
+                    const int v = (int)tile[(py * A.stride + r + kPatch / 2) * tw +
+                                            px * A.stride + c + kPatch / 2];
+                    const int key = ((v + 32768) << 12) | (4095 - e);
+                    best = key > best ? key : best;
+                }
+            }
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) {
+                const int other = __shfl_xor(best, o, 64);
+                best = other > best ? other : best;
+            }
+            const int e = 4095 - (best & 4095);
+            const int r = e / A.stride, c = e - r * A.stride;
+            cy = li * A.stride + r;
+            cx = lj * A.stride + c;
+            or_ = py * A.stride + r;
+            oc = px * A.stride + c;
+        }
+        const float zc = tile[(or_ + kPatch / 2) * tw + oc + kPatch / 2];
+
+        // ---- conv1: one MFMA per output row oy (16 output columns)
+#pragma unroll 4
+        for (int oy = 0; oy < 16; oy++) {
+            const float *src = tile + (or_ + 4 * oy + hi) * tw + oc + 4 * lo;
+            // elevation differences in units of 256 m (exact power-of-two scale)
+            constexpr float kScale = 0.00390625f;
+            const float v0 = (src[0] - zc) * kScale, v1 = (src[1] - zc) * kScale;
+            const float v2 = (src[2] - zc) * kScale, v3 = (src[3] - zc) * kScale;
+            const s4 a = pack4(v0, v1, v2, v3);
+            if (kTrain) {
+                uint16_t *ps = A.Pst + pid * 4096 + (4 * oy + hi) * 64 + 4 * lo;
+                ps[0] = (uint16_t)a.x; ps[1] = (uint16_t)a.y;
+                ps[2] = (uint16_t)a.z; ps[3] = (uint16_t)a.w;
+            }
+            f4 c = mfma(a, bw1, f4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int ox = 4 * hi + i;
+                const uint16_t h = (uint16_t)bf16_bits(fmaxf(c[i] + b1, 0.f));
+                H1[(oy * 16 + ox) * 16 + lo] = h;
+                if (kTrain)
+                    A.H1st[(pid * 256 + oy * 16 + ox) * 16 + lo] = h;
+            }
+        }
+        wave_lds_sync();
+        // ---- conv2: 49 output positions in 4 row tiles, 9 taps of 16 channels
+#pragma unroll 1
+        for (int t = 0; t < 4; t++) {
+            int m = 16 * t + lo;
+            m = m > 48 ? 48 : m;
+            const int oy = m / 7, ox = m - oy * 7;
+            f4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int tap = 0; tap < 9; tap++) {
+                const int ky = tap / 3, kx = tap - ky * 3;
+                const uint16_t *src = H1 + ((2 * oy + ky) * 16 + (2 * ox + kx)) * 16 + 4 * hi;
+                s4 a;
+                a.x = (short)src[0]; a.y = (short)src[1]; a.z = (short)src[2]; a.w = (short)src[3];
+                c = mfma(a, bw2[tap], c);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int pos = 16 * t + 4 * hi + i;
+                if (pos < 49) {
+                    const uint16_t h = (uint16_t)bf16_bits(fmaxf(c[i] + b2, 0.f));
+                    H2[pos * 16 + lo] = h;
+                    if (kTrain)
+                        A.H2st[(pid * 49 + pos) * 16 + lo] = h;
+                }
+            }
+        }
+        wave_lds_sync();
+        // ---- conv3: 9 output positions, 2 column tiles of 16 channels
+        f4 c3[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+        {
+            int m = lo > 8 ? 8 : lo;
+            const int oy = m / 3, ox = m - oy * 3;
+#pragma unroll
+            for (int tap = 0; tap < 9; tap++) {
+                const int ky = tap / 3, kx = tap - ky * 3;
+                const uint16_t *src = H2 + ((2 * oy + ky) * 7 + (2 * ox + kx)) * 16 + 4 * hi;
+                s4 a;
+                a.x = (short)src[0]; a.y = (short)src[1]; a.z = (short)src[2]; a.w = (short)src[3];
+                c3[0] = mfma(a, bw3[tap][0], c3[0]);
+                c3[1] = mfma(a, bw3[tap][1], c3[1]);
+            }
+        }
+        // ---- ReLU, global average pool over the 9 positions, FC
+        float y = 0.f;
+#pragma unroll
+        for (int nt = 0; nt < 2; nt++) {
+            float s = 0.f;
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int pos = 4 * hi + i;
+                const float h = fmaxf(c3[nt][i] + b3[nt], 0.f);
+                if (pos < 9) {
+                    s += h;
+                    if (kTrain)
+                        A.H3st[(pid * 9 + pos) * 32 + nt * 16 + lo] = h;
+                }
+            }
+            s += __shfl_xor(s, 16, 64);
+            s += __shfl_xor(s, 32, 64);
+            const float g = s / 9.0f;
+            if (kTrain && hi == 0)
+                A.gst[pid * 32 + nt * 16 + lo] = g;
+            y += wfc[nt] * g;
+        }
+        // sum over the 16 channels of the lane group (all groups agree)
+        y += __shfl_xor(y, 1, 64);
+        y += __shfl_xor(y, 2, 64);
+        y += __shfl_xor(y, 4, 64);
+        y += __shfl_xor(y, 8, 64);
+        y += bfc;
+        if (lane == 0) {
+            if (kTrain)
+                A.yst[pid] = y;
+            else
+                A.score[pid] = 1.0f / (1.0f + __expf(-y));
+        }
+        wave_lds_sync();
+    }
+}
+
+// --------------------------------------------------------------- backward
+// Head: p = sigmoid(y); dL/dy of the mean squared error; the gradient of
+// the pooled features spread over the 9 conv3 positions through the ReLU.
+__global__ void cnn_head_bwd(const float *__restrict__ params, const float *__restrict__ y,
+                             const float *__restrict__ labels, const float *__restrict__ H3,
+                             int64_t B, float *__restrict__ dy, float *__restrict__ sq,
+                             uint16_t *__restrict__ dA3)
+{
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B)
+        return;
+    const float pr = 1.0f / (1.0f + __expf(-y[b]));
+    const float e = pr - labels[b];
+    const float d = 2.0f * e / (float)B * pr * (1.0f - pr);
+    dy[b] = d;
+    sq[b] = e * e;
+    for (int pos = 0; pos < 9; pos++)
+        for (int co = 0; co < 32; co++) {
+            const float h = H3[(b * 9 + pos) * 32 + co];
+            const float v = h > 0.f ? d * params[OWFC + co] / 9.0f : 0.f;
+            dA3[(b * 9 + pos) * 32 + co] = (uint16_t)bf16_bits(v);
+        }
+}
+
+// Generic MFMA "gather GEMM": C[m][n] = sum_k A(m, k) * B(k, n) over k-blocks
+// of 16, one wavefront per (16 x 16 tile, k-split); partial results go to
+// out[split][m][n] and are summed later in a fixed order (deterministic).
+template <class Op>
+__global__ __launch_bounds__(256) void gemm_kernel(Op op)
+{
+    const int lane = threadIdx.x & 63, lo = lane & 15, hi = lane >> 4;
+    const int64_t wg = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t ntile = (int64_t)op.MT * op.NT;
+    if (wg >= ntile * op.S)
+        return;
+    const int tile = (int)(wg % ntile), split = (int)(wg / ntile);
+    const int mt = tile / op.NT, nt = tile % op.NT;
+    const int64_t kb0 = (int64_t)split * op.KS;
+    const int64_t kb1 = kb0 + op.KS < op.KB ? kb0 + op.KS : op.KB;
+    f4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int64_t kb = kb0; kb < kb1; kb++) {
+        const int64_t k = kb * 16 + 4 * hi;
+        acc = mfma(op.a(mt * 16 + lo, k), op.b(k, nt * 16 + lo), acc);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+        op.store(split, mt * 16 + 4 * hi + i, nt * 16 + lo, acc[i]);
+}
+
+__device__ __forceinline__ s4 load4_strided(const uint16_t *p, int64_t stride, int64_t valid)
+{
+    s4 r;
+    r.x = valid > 0 ? (short)p[0] : (short)0;
+    r.y = valid > 1 ? (short)p[stride] : (short)0;
+    r.z = valid > 2 ? (short)p[2 * stride] : (short)0;
+    r.w = valid > 3 ? (short)p[3 * stride] : (short)0;
+    return r;
+}
+
+// backward-weight: dW[co][tap*CI + ci] = sum_rows dA[row][co] * X(row, tap, ci)
+// rows = samples x output positions (OH x OH).  X gathers the layer input
+// (the bf16 patch for conv1).  KW is the kernel width.
+template <int OH, int CO, int IH, int CI, int KW, int STRIDE, bool kPatchIn>
+struct WgradOp {
+    const uint16_t *dA;  // [rows][CO] bf16
+    const uint16_t *X;   // layer input, bf16: [B][IH*IH][CI] (or the patch [B][64][64])
+    float *part;         // [S][CO][N]
+    int64_t rows;
+    int MT, NT, S;
+    int64_t KB, KS;      // k-blocks in total and per split
+    static constexpr int N = KW * KW * CI;
+    __device__ s4 a(int m, int64_t k) const
+    {
+        return load4_strided(dA + k * CO + m, CO, rows - k);
+    }
+    __device__ s4 b(int64_t k, int n) const
+    {
+        const int tap = n / CI, ci = n - tap * CI;
+        const int ky = tap / KW, kx = tap - ky * KW;
+        short e[4];
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const int64_t row = k + i;
+            if (row >= rows) {
+                e[i] = 0;
+                continue;
+            }
+            const int64_t smp = row / (OH * OH);
+            const int pos = (int)(row - smp * (OH * OH));
+            const int oy = pos / OH, ox = pos - oy * OH;
+            const int iy = STRIDE * oy + ky, ix = STRIDE * ox + kx;
+            e[i] = kPatchIn ? (short)X[smp * 4096 + iy * 64 + ix]
+                            : (short)X[(smp * (IH * IH) + iy * IH + ix) * CI + ci];
+        }
+        return s4{e[0], e[1], e[2], e[3]};
+    }
+    __device__ void store(int split, int m, int n, float v) const
+    {
+        if (m < CO && n < N)
+            part[((int64_t)split * CO + m) * N + n] = v;
+    }
+};
+
+// backward-data columns: col[row][tap*CI + ci] = sum_co dA[row][co] * W[co][tap][ci]
+template <int CO, int CI, int KW>
+struct ColOp {
+    const uint16_t *dA;   // [rows][CO]
+    const uint16_t *W;    // bf16 [CO][KW*KW][CI]
+    float *col;           // [rows][N]
+    int64_t rows;
+    int MT, NT, S;
+    int64_t KB, KS;
+    static constexpr int N = KW * KW * CI;
+    __device__ s4 a(int64_t m, int64_t k) const
+    {
+        if (m >= rows)
+            return s4{0, 0, 0, 0};
+        const uint16_t *p = dA + m * CO + k;
+        return s4{(short)p[0], (short)p[1], (short)p[2], (short)p[3]};
+    }
+    __device__ s4 b(int64_t k, int n) const
+    {
+        return load4_strided(W + k * N + n, N, CO - k);
+    }
+    __device__ void store(int, int64_t m, int n, float v) const
+    {
+        if (m < rows)
+            col[m * N + n] = v;
+    }
+};
+
+// col2im gather for a 3x3 stride-2 layer: dX[s][iy][ix][ci] = sum over the
+// (output position, tap) pairs reading (iy, ix), then the ReLU mask of the
+// layer input, rounded to bf16 as the next MFMA consumes it.
+template <int OH, int IH, int CI>
+__global__ void col2im_relu(const float *__restrict__ col, const uint16_t *__restrict__ Xin,
+                            int64_t B, uint16_t *__restrict__ dAin)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= B * IH * IH * CI)
+        return;
+    const int ci = (int)(e % CI);
+    const int64_t sp = e / CI;
+    const int pos = (int)(sp % (IH * IH));
+    const int64_t s = sp / (IH * IH);
+    const int iy = pos / IH, ix = pos - iy * IH;
+    float acc = 0.f;
+    for (int ky = 0; ky < 3; ky++) {
+        const int ty = iy - ky;
+        if (ty < 0 || (ty & 1) || (ty >> 1) >= OH)
+            continue;
+        for (int kx = 0; kx < 3; kx++) {
+            const int tx = ix - kx;
+            if (tx < 0 || (tx & 1) || (tx >> 1) >= OH)
+                continue;
+            const int64_t row = s * (OH * OH) + (ty >> 1) * OH + (tx >> 1);
+            acc += col[row * (9 * CI) + (ky * 3 + kx) * CI + ci];
+        }
+    }
+    const float x = bf16_float(Xin[e]);
+    dAin[e] = (uint16_t)bf16_bits(x > 0.f ? acc : 0.f);
+}
+
+// Fixed-order sums: out[j] = sum_s part[s][j] (weights), and bias / head
+// gradients as column sums over rows.
+__global__ void sum_partials(const float *__restrict__ part, int S, int64_t n,
+                             float *__restrict__ out)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n)
+        return;
+    float s = 0.f;
+    for (int k = 0; k < S; k++)
+        s += part[(int64_t)k * n + j];
+    out[j] = s;
+}
+
+// column sums of a bf16 [rows][C] matrix into out[C] (one workgroup per
+// column, fixed-order tree inside the workgroup)
+__global__ void colsum_bf16(const uint16_t *__restrict__ m, int64_t rows, int C,
+                            float *__restrict__ out)
+{
+    __shared__ float red[256];
+    const int c = blockIdx.x;
+    float s = 0.f;
+    for (int64_t r = threadIdx.x; r < rows; r += 256)
+        s += bf16_float(m[r * C + c]);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        out[c] = red[0];
+}
+
+// FC head gradients and the loss: dWfc[co] = sum_b dy_b g_b[co],
+// dbfc = sum_b dy_b, loss = mean_b sq_b (one workgroup, fixed order).
+__global__ void head_grads(const float *__restrict__ dy, const float *__restrict__ g,
+                           const float *__restrict__ sq, int64_t B, float *__restrict__ grad,
+                           float *__restrict__ loss)
+{
+    __shared__ float red[256];
+    for (int j = 0; j < 34; j++) {
+        float s = 0.f;
+        for (int64_t b = threadIdx.x; b < B; b += 256)
+            s += j < 32 ? dy[b] * g[b * 32 + j] : (j == 32 ? dy[b] : sq[b]);
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (threadIdx.x < w)
+                red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            if (j < 32)
+                grad[OWFC + j] = red[0];
+            else if (j == 32)
+                grad[OBFC] = red[0];
+            else if (loss)
+                *loss = red[0] / (float)B;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void sigmoid_kernel(const float *__restrict__ y, int64_t n, float *__restrict__ p)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        p[i] = 1.0f / (1.0f + __expf(-y[i]));
+}
+
+__global__ void to_bf16(const float *__restrict__ x, int64_t n, uint16_t *__restrict__ y)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        y[i] = (uint16_t)bf16_bits(x[i]);
+}
+
+// Adam (Kingma & Ba) with bias correction; step counts from 1.
+__global__ void adam_kernel(float *__restrict__ p, float *__restrict__ m, float *__restrict__ v,
+                            const float *__restrict__ g, int64_t n, float lr, float b1, float b2,
+                            float eps, float c1, float c2)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// ----------------------------------------------------------- workspace
+struct Ws {
+    uint16_t *P, *H1, *H2, *dA3, *dA2, *dA1, *wbf;
+    float *H3, *g, *y, *dy, *sq, *col, *part;
+    size_t bytes;
+};
+
+constexpr int kMaxSplits = 64;
+constexpr int64_t kPartFloats = (int64_t)kMaxSplits * 32 * 144;
+
+static size_t al(size_t v) { return (v + 255) & ~(size_t)255; }
+
+static Ws ws_layout(int64_t B, void *base)
+{
+    Ws w{};
+    size_t o = 0;
+    char *c = reinterpret_cast<char *>(base);
+    auto take = [&](size_t bytes) { char *p = c ? c + o : nullptr; o += al(bytes); return p; };
+    w.P = (uint16_t *)take((size_t)B * 4096 * 2);
+    w.H1 = (uint16_t *)take((size_t)B * 256 * 16 * 2);
+    w.H2 = (uint16_t *)take((size_t)B * 49 * 16 * 2);
+    w.H3 = (float *)take((size_t)B * 9 * 32 * 4);
+    w.g = (float *)take((size_t)B * 32 * 4);
+    w.y = (float *)take((size_t)B * 4);
+    w.dy = (float *)take((size_t)B * 4);
+    w.sq = (float *)take((size_t)B * 4);
+    w.dA3 = (uint16_t *)take((size_t)B * 9 * 32 * 2);
+    w.dA2 = (uint16_t *)take((size_t)B * 49 * 16 * 2);
+    w.dA1 = (uint16_t *)take((size_t)B * 256 * 16 * 2);
+    w.col = (float *)take((size_t)B * 49 * 144 * 4);
+    w.part = (float *)take((size_t)kPartFloats * 4);
+    w.wbf = (uint16_t *)take((size_t)NPARAMS * 2);
+    w.bytes = o;
+    return w;
+}
+
+template <class Op>
+static int launch_gemm(Op op, hipStream_t s, const char *what)
+{
+    const int64_t waves = (int64_t)op.MT * op.NT * op.S;
+    hipLaunchKernelGGL(gemm_kernel<Op>, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, op);
+    return check_launch(what);
+}
+
+// split count so that each wavefront does ~64 k-blocks, at most kMaxSplits
+static void pick_splits(int64_t KB, int &S, int64_t &KS)
+{
+    S = (int)std::min<int64_t>(kMaxSplits, std::max<int64_t>(1, (KB + 63) / 64));
+    KS = (KB + S - 1) / S;
+}
+
+}  // namespace
+}  // namespace siting
+
+using namespace siting;
+
+extern "C" int siting_cnn_param_count(void) { return NPARAMS; }
+
+extern "C" size_t siting_cnn_workspace_size(int64_t batch)
+{
+    if (batch < 1)
+        return 0;
+    return ws_layout(batch, nullptr).bytes;
+}
+
+static int check_terrain(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
+                         const char *fn)
+{
+    SITING_REQUIRE(z != nullptr, "%s: NULL terrain", fn);
+    SITING_REQUIRE(nrows >= 1 && ncols >= 1 && ld >= ncols, "%s: bad terrain shape", fn);
+    return SITING_OK;
+}
+
+extern "C" int siting_cnn_forward(const float *params, const int16_t *z, int64_t nrows,
+                                  int64_t ncols, int64_t ld, const int64_t *centres, int64_t B,
+                                  float *pred, void *ws, size_t ws_bytes, void *stream)
+{
+    clear_error();
+    const char *fn = "siting_cnn_forward";
+    int rc = check_terrain(z, nrows, ncols, ld, fn);
+    if (rc != SITING_OK)
+        return rc;
+    SITING_REQUIRE(params && centres && B >= 1, "%s: NULL pointer or empty batch", fn);
+    if (!ws || ws_bytes < siting_cnn_workspace_size(B)) {
+        set_error("%s: workspace of %zu bytes needed", fn, siting_cnn_workspace_size(B));
+        return SITING_E_WORKSPACE;
+    }
+    Ws w = ws_layout(B, ws);
+    FwdArgs a{};
+    a.params = params; a.z = z; a.nrows = nrows; a.ncols = ncols; a.ld = ld;
+    a.centres = centres; a.nposts = B;
+    a.Pst = w.P; a.H1st = w.H1; a.H2st = w.H2; a.H3st = w.H3; a.gst = w.g; a.yst = w.y;
+    hipStream_t s = as_stream(stream);
+    const size_t lds = kFwdWaves * ((256 * 16 + 64 * 16) * 2 + kPatch * kPatch * 4);
+    const int64_t grid = std::min<int64_t>((B + kFwdWaves - 1) / kFwdWaves,
+                                           (int64_t)device_cus() * 8);
+    hipLaunchKernelGGL(cnn_fwd_kernel<true>, dim3((unsigned)grid), dim3(64 * kFwdWaves), lds, s, a);
+    rc = check_launch("cnn_fwd_kernel");
+    if (rc != SITING_OK || !pred)
+        return rc;
+    hipLaunchKernelGGL(sigmoid_kernel, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, w.y, B,
+                       pred);
+    return check_launch("cnn_sigmoid");
+}
+
+extern "C" int siting_cnn_backward(const float *params, const float *labels, int64_t B,
+                                   float *grad, float *loss, void *ws, size_t ws_bytes,
+                                   void *stream)
+{
+    clear_error();
+    const char *fn = "siting_cnn_backward";
+    SITING_REQUIRE(params && labels && grad && B >= 1, "%s: NULL pointer or empty batch", fn);
+    if (!ws || ws_bytes < siting_cnn_workspace_size(B)) {
+        set_error("%s: workspace of %zu bytes needed", fn, siting_cnn_workspace_size(B));
+        return SITING_E_WORKSPACE;
+    }
+    Ws w = ws_layout(B, ws);
+    hipStream_t s = as_stream(stream);
+    int rc;
+    hipLaunchKernelGGL(to_bf16, dim3((NPARAMS + 255) / 256), dim3(256), 0, s, params,
+                       (int64_t)NPARAMS, w.wbf);
+    if ((rc = check_launch("to_bf16")) != SITING_OK)
+        return rc;
+    hipLaunchKernelGGL(cnn_head_bwd, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, params,
+                       w.y, labels, w.H3, B, w.dy, w.sq, w.dA3);
+    if ((rc = check_launch("cnn_head_bwd")) != SITING_OK)
+        return rc;
+    hipLaunchKernelGGL(head_grads, dim3(1), dim3(256), 0, s, w.dy, w.g, w.sq, B, grad, loss);
+    if ((rc = check_launch("head_grads")) != SITING_OK)
+        return rc;
+
+    // ---- conv3: weights, bias, then data gradient into H2's positions
+    {
+        WgradOp<3, 32, 7, 16, 3, 2, false> op{};
+        op.dA = w.dA3; op.X = w.H2; op.part = w.part; op.rows = B * 9;
+        op.MT = 2; op.NT = 9; op.KB = (op.rows + 15) / 16;
+        pick_splits(op.KB, op.S, op.KS);
+        if ((rc = launch_gemm(op, s, "wgrad3")) != SITING_OK)
+            return rc;
+        hipLaunchKernelGGL(sum_partials, dim3((32 * 144 + 255) / 256), dim3(256), 0, s, w.part,
+                           op.S, (int64_t)32 * 144, grad + OW3);
+        if ((rc = check_launch("sum_partials")) != SITING_OK)
+            return rc;
+        hipLaunchKernelGGL(colsum_bf16, dim3(32), dim3(256), 0, s, w.dA3, B * 9, 32, grad + OB3);
+        if ((rc = check_launch("colsum_bf16")) != SITING_OK)
+            return rc;
+        ColOp<32, 16, 3> cop{};
+        cop.dA = w.dA3; cop.W = w.wbf + OW3; cop.col = w.col; cop.rows = B * 9;
+        cop.MT = (int)((cop.rows + 15) / 16); cop.NT = 9; cop.S = 1; cop.KB = 2; cop.KS = 2;
+        if ((rc = launch_gemm(cop, s, "col3")) != SITING_OK)
+            return rc;
+        const int64_t n2 = B * 49 * 16;
+        hipLaunchKernelGGL((col2im_relu<3, 7, 16>), dim3((unsigned)((n2 + 255) / 256)), dim3(256),
+                           0, s, w.col, w.H2, B, w.dA2);
+        if ((rc = check_launch("col2im3")) != SITING_OK)
+            return rc;
+    }
+    // ---- conv2
+    {
+        WgradOp<7, 16, 16, 16, 3, 2, false> op{};
+        op.dA = w.dA2; op.X = w.H1; op.part = w.part; op.rows = B * 49;
+        op.MT = 1; op.NT = 9; op.KB = (op.rows + 15) / 16;
+        pick_splits(op.KB, op.S, op.KS);
+        if ((rc = launch_gemm(op, s, "wgrad2")) != SITING_OK)
+            return rc;
+        hipLaunchKernelGGL(sum_partials, dim3((16 * 144 + 255) / 256), dim3(256), 0, s, w.part,
+                           op.S, (int64_t)16 * 144, grad + OW2);
+        if ((rc = check_launch("sum_partials")) != SITING_OK)
+            return rc;
+        hipLaunchKernelGGL(colsum_bf16, dim3(16), dim3(256), 0, s, w.dA2, B * 49, 16, grad + OB2);
+        if ((rc = check_launch("colsum_bf16")) != SITING_OK)
+            return rc;
+        ColOp<16, 16, 3> cop{};
+        cop.dA = w.dA2; cop.W = w.wbf + OW2; cop.col = w.col; cop.rows = B * 49;
+        cop.MT = (int)((cop.rows + 15) / 16); cop.NT = 9; cop.S = 1; cop.KB = 1; cop.KS = 1;
+        if ((rc = launch_gemm(cop, s, "col2")) != SITING_OK)
+            return rc;
+        const int64_t n1 = B * 256 * 16;
+        hipLaunchKernelGGL((col2im_relu<7, 16, 16>), dim3((unsigned)((n1 + 255) / 256)),
+                           dim3(256), 0, s, w.col, w.H1, B, w.dA1);
+        if ((rc = check_launch("col2im2")) != SITING_OK)
+            return rc;
+    }
+    // ---- conv1 (weights and bias only; the input needs no gradient)
+    {
+        WgradOp<16, 16, 64, 1, 4, 4, true> op{};
+        op.dA = w.dA1; op.X = w.P; op.part = w.part; op.rows = B * 256;
+        op.MT = 1; op.NT = 1; op.KB = (op.rows + 15) / 16;
+        pick_splits(op.KB, op.S, op.KS);
+        if ((rc = launch_gemm(op, s, "wgrad1")) != SITING_OK)
+            return rc;
+        hipLaunchKernelGGL(sum_partials, dim3(1), dim3(256), 0, s, w.part, op.S, (int64_t)256,
+                           grad + OW1);
+        if ((rc = check_launch("sum_partials")) != SITING_OK)
+            return rc;
+        hipLaunchKernelGGL(colsum_bf16, dim3(16), dim3(256), 0, s, w.dA1, B * 256, 16, grad + OB1);
+        if ((rc = check_launch("colsum_bf16")) != SITING_OK)
+            return rc;
+    }
+    return SITING_OK;
+}
+
+extern "C" int siting_cnn_adam(float *params, float *m, float *v, const float *grad, int64_t n,
+                               int32_t step, float lr, float beta1, float beta2, float eps,
+                               void *stream)
+{
+    clear_error();
+    SITING_REQUIRE(params && m && v && grad, "siting_cnn_adam: NULL pointer");
+    SITING_REQUIRE(n >= 1 && step >= 1, "siting_cnn_adam: n and step must be >= 1");
+    SITING_REQUIRE(lr > 0.f && beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f &&
+                       eps > 0.f, "siting_cnn_adam: bad hyper-parameters");
+    const float c1 = 1.f - powf(beta1, (float)step), c2 = 1.f - powf(beta2, (float)step);
+    hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                       as_stream(stream), params, m, v, grad, n, lr, beta1, beta2, eps, c1, c2);
+    return check_launch("adam_kernel");
+}
+
+extern "C" int siting_cnn_score_terrain(const float *params, const int16_t *z, int64_t nrows,
+                                        int64_t ncols, int64_t ld, int32_t stride, float *score,
+                                        void *stream)
+{
+    clear_error();
+    const char *fn = "siting_cnn_score_terrain";
+    int rc = check_terrain(z, nrows, ncols, ld, fn);
+    if (rc != SITING_OK)
+        return rc;
+    SITING_REQUIRE(params && score, "%s: NULL pointer", fn);
+    SITING_REQUIRE(stride >= 1 && stride <= 64, "%s: stride %d outside 1..64", fn, stride);
+    FwdArgs a{};
+    a.params = params; a.z = z; a.nrows = nrows; a.ncols = ncols; a.ld = ld;
+    a.stride = stride;
+    a.BL = stride <= 8 ? 8 : (stride <= 24 ? 4 : 2);
+    a.lat_r = (nrows + stride - 1) / stride;
+    a.lat_c = (ncols + stride - 1) / stride;
+    const int64_t blocks_r = (a.lat_r + a.BL - 1) / a.BL;
+    a.blocks_c = (a.lat_c + a.BL - 1) / a.BL;
+    a.score = score;
+    const int tw = a.BL * stride + kPatch - 1;
+    const size_t lds = kFwdWaves * (256 * 16 + 64 * 16) * 2 + (size_t)tw * tw * 4;
+    if ((int64_t)lds > device_max_lds()) {
+        set_error("%s: tile does not fit in LDS", fn);
+        return SITING_E_UNSUPPORTED;
+    }
+    const int64_t grid = blocks_r * a.blocks_c;
+    if (grid > INT32_MAX) {
+        set_error("%s: terrain too large", fn);
+        return SITING_E_UNSUPPORTED;
+    }
+    hipLaunchKernelGGL(cnn_fwd_kernel<false>, dim3((unsigned)grid), dim3(64 * kFwdWaves), lds,
+                       as_stream(stream), a);
+    return check_launch("cnn_fwd_kernel");
+}

@@ -7,7 +7,8 @@
 //   f32 keys: ord(score) << 32 | (2^32-1 - local)
 // where local is the row-major index inside the block (same order as the
 // global linear index) and ord() maps floats to order-preserving unsigned
-// integers (NaN as -infinity).  Every lane streams its share of the block
+// integers (NaN as -infinity).  f32 keys score the cells of a stride grid;
+// a winning cell is returned as its highest post.  Every lane streams its share of the block
 // keeping a sorted register top-k; a threshold test makes insertions rare.
 // The per-lane lists are then merged by k rounds of a workgroup argmax in
 // which the winning lane pops its list head.
@@ -125,7 +126,21 @@ __global__ __launch_bounds__(kFmThreads) void findmax_kernel(
                                       : (0xFFFFFFFFFFull - (best & 0xFFFFFFFFFFull));
                 int64_t ly = lr0 + (int64_t)(local / (uint64_t)bw);
                 int64_t lx = lc0 + (int64_t)(local % (uint64_t)bw);
-                out = kF32 ? (ly * stride) * ncols + lx * stride : ly * ncols + lx;
+                if (kF32) {
+                    // the cell stands for its highest post (elevation desc,
+                    // index asc)
+                    int bz = -32769;
+                    for (int64_t y = ly * stride; y < (ly + 1) * stride && y < nrows; y++)
+                        for (int64_t x = lx * stride; x < (lx + 1) * stride && x < ncols; x++) {
+                            const int v = z[y * ld + x];
+                            if (v > bz) {
+                                bz = v;
+                                out = y * ncols + x;
+                            }
+                        }
+                } else {
+                    out = ly * ncols + lx;
+                }
             }
             cand[blk * k + rank] = out;
         }
@@ -147,10 +162,9 @@ extern "C" int siting_findmax(const void *key, int32_t key_type, int32_t key_str
     SITING_REQUIRE(key != nullptr && cand != nullptr, "siting_findmax: NULL key or output");
     SITING_REQUIRE(key_type == SITING_KEY_U8 || key_type == SITING_KEY_F32,
                    "siting_findmax: unknown key_type %d", key_type);
-    SITING_REQUIRE(key_type == SITING_KEY_F32 || z != nullptr,
-                   "siting_findmax: u8 keys need the terrain for tie-breaking");
+    SITING_REQUIRE(z != nullptr, "siting_findmax: NULL terrain");
     SITING_REQUIRE(nrows >= 1 && ncols >= 1, "siting_findmax: empty terrain");
-    SITING_REQUIRE(key_type == SITING_KEY_F32 || ld >= ncols, "siting_findmax: ld < ncols");
+    SITING_REQUIRE(ld >= ncols, "siting_findmax: ld < ncols");
     SITING_REQUIRE(key_stride >= 1, "siting_findmax: key_stride must be >= 1");
     SITING_REQUIRE(key_type == SITING_KEY_F32 || key_stride == 1,
                    "siting_findmax: u8 keys need key_stride 1");

@@ -69,10 +69,12 @@ def test_bf16_rounding_rules():
 def test_patch_centre_and_clamp():
     z = np.arange(100 * 90, dtype=np.int64).reshape(100, 90).astype(np.int16)
     P = cnn.patches(z, [0, 50 * 90 + 45], round=False)
+    assert P.shape == (2, 64, 64)
     assert P[0, 32, 32] == 0 and P[1, 32, 32] == 0
     # clamped corner: the rows above the terrain repeat row 0
     assert (P[0, :32, 32] == 0).all()
-    assert np.isclose(P[1, 33, 32], 90e-3) and np.isclose(P[1, 32, 33], 1e-3)
+    assert P[1, 33, 32] == 90 / 256 and P[1, 32, 33] == 1 / 256
+    assert P[1, 0, 0] == (-32 * 90 - 32) / 256
 
 
 def test_adam_first_step_is_signed_lr():

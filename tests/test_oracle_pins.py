@@ -221,7 +221,7 @@ def test_findmax_lexsort(orc, shape, gr, gc, k):
 
 def test_findmax_f32_strided(orc):
     rng = np.random.default_rng(4)
-    z = rng.integers(0, 9, size=(23, 29)).astype(np.int16)
+    z = rng.integers(0, 9, size=(23, 29)).astype(np.int16)       # many elevation ties
     s = 3
     kr, kc = -(-23 // s), -(-29 // s)
     sc = rng.integers(0, 5, size=(kr, kc)).astype(np.float32)
@@ -238,7 +238,14 @@ def test_findmax_f32_strided(orc):
                     v = float(sc[y // s, x // s])
                     items.append((-(v if v == v else -np.inf), y * 29 + x))
         items.sort()
-        want = [i for _, i in items[:4]] + [-1] * max(0, 4 - len(items))
+        # each winning cell stands for its highest post (elevation desc, index asc)
+        want = []
+        for _, i in items[:4]:
+            y0, x0 = divmod(i, 29)
+            cell = [(-int(z[y, x]), y * 29 + x) for y in range(y0, min(y0 + s, 23))
+                    for x in range(x0, min(x0 + s, 29))]
+            want.append(min(cell)[1])
+        want += [-1] * max(0, 4 - len(items))
         assert got[b * 4:(b + 1) * 4].tolist() == want
 
 
