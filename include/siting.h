@@ -216,11 +216,13 @@ int siting_autotune_candidates(int32_t rmax, siting_schedule *out_host, int32_t 
  * viewshed C, repeatedly take the candidate with the largest gain
  * |V_i \ C| (ties to the smallest candidate index), record it and set
  * C |= V_i; stop after max_obs observers, once |C| >= target_cells, or
- * when the best gain is 0.  Evaluated lazily: a stale gain is an upper bound
- * of the current one (the stage's stated optimisation), so the selection is
- * exactly the plain greedy one.
+ * when the best gain is 0.  Evaluated lazily with the stage's stated bound
+ * (a gain can only shrink as C grows, so a stale gain is an upper bound):
+ * the top candidate is taken only once its gain is fresh, which makes the
+ * selection exactly the plain greedy one; stale tops are re-evaluated 16 at
+ * a time.
  *   bitmaps/offsets/obs : as produced by siting_viewshed_batch (device)
- *   n < 2^32; windows must be those of the same nrows x ncols terrain; a
+ *   n < 2^32-1; windows must be those of the same nrows x ncols terrain; a
  *   record with a position or roi out of range counts as gaining nothing
  *   cumulative : out (device) uint64[nrows * ceil(ncols/64)], overwritten
  *   selected, gains : out (device) int64[max_obs]; entries past *nselected

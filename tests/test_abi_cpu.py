@@ -55,6 +55,7 @@ def test_validation_errors_before_launch():
                              fake, 8, None) == -4
     assert lib.siting_greedy(fake, fake, fake, 0, 10, 10, 3, 100, fake, fake, fake, fake,
                              fake, 1 << 20, None) == -1
+    assert lib.siting_greedy_workspace_size(100) >= 100 * 12
 
 
 def test_layout_matches_oracle_and_rejects_bad_observers(orc):

@@ -172,13 +172,17 @@ def test_autotune_returns_a_candidate(S, orc):
 
 
 # --------------------------------------------------------------- SITE ------
-@pytest.mark.parametrize("seed,n_obs,max_obs,frac", [(1, 400, 60, 1.0), (2, 300, 1000, 0.5),
-                                                     (3, 50, 200, 1.0)])
-def test_greedy_parity(S, orc, seed, n_obs, max_obs, frac):
-    _say("greedy", seed, n_obs, max_obs, frac)
+@pytest.mark.parametrize("seed,n_obs,max_obs,frac,roi", [
+    (1, 400, 60, 1.0, (20, 90)), (2, 300, 1000, 0.5, (20, 90)), (3, 50, 200, 1.0, (20, 90)),
+    (4, 3000, 400, 1.0, (5, 40)),     # dense: hundreds of windows meet each winner
+    (5, 1, 5, 1.0, (30, 30)),         # a single candidate
+    (6, 700, 300, 1.0, (1, 250)),     # very uneven ROIs (bucket side from the largest)
+])
+def test_greedy_parity(S, orc, seed, n_obs, max_obs, frac, roi):
+    _say("greedy", seed, n_obs, max_obs, frac, roi)
     from synth import uniform_observers
     z = _terrain(500, 2.4, 1500, seed)
-    obs = uniform_observers(500, 500, n_obs, seed, roi=(20, 90), height=(5, 30))
+    obs = uniform_observers(500, 500, n_obs, seed, roi=roi, height=(5, 30))
     bm_h, off = orc.viewshed(z, obs)
     tgt = 500 * 500 if frac >= 1 else int(math.ceil(frac * 500 * 500))
     wsel, wgain, wcum, _ = orc.greedy(bm_h, off, obs, 500, 500, max_obs, tgt, lazy=True)
