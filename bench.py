@@ -131,6 +131,8 @@ def main():
                     help="pick the viewshed schedule with the autotuner before timing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy (counter calibration for rocprof)")
+    ap.add_argument("--surrogate-stride", type=int, default=8,
+                    help="cell size of the CNN-ranked leg (0 skips that leg)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -224,6 +226,32 @@ def main():
         "hbm_frac": (cells * 2 + bm_bytes) / vs_s / 1e9 / PEAK_HBM_GBS,
     }
 
+    # surrogate-ranked leg: the same path with the CNN score of the cells of
+    # a stride grid as the FINDMAX key (weights trained on 4096^2 terrains)
+    sur = None
+    if args.surrogate_stride > 0:
+        from paper_2006_16783_amd import surrogate as SG
+        params = SG.load_weights(device=dev)
+        P.run(z, cfg, surrogate=(params, args.surrogate_stride))
+        torch.cuda.synchronize()
+        sur_tot, sres = {}, None
+        t1 = time.perf_counter()
+        for i in range(args.steps):
+            sres = P.run(z, cfg, surrogate=(params, args.surrogate_stride))
+            for k, v in sres.stage_ms.items():
+                sur_tot[k] = sur_tot.get(k, 0.0) + v
+            log(f"[bench] surrogate step {i}: {sres.stage_ms}")
+        torch.cuda.synchronize()
+        sur_ms = (time.perf_counter() - t1) * 1e3 / args.steps
+        sur = {"siting_wall_s": sur_ms / 1e3, "ms_per_step": sur_ms, "stride": args.surrogate_stride,
+               "stage_ms": {k: v / args.steps for k, v in sur_tot.items()},
+               "selected": int(len(sres.selected)), "candidates": int(len(sres.observers)),
+               "coverage_frac": sres.coverage_cells / (nr * nc),
+               "plain_coverage_frac": last.coverage_cells / (nr * nc),
+               "coverage_diff_pp": 100.0 * (sres.coverage_cells - last.coverage_cells) / (nr * nc),
+               "speedup_vs_plain": ms_per_step / sur_ms,
+               "weights": "paper_2006_16783_amd/weights/surrogate_r100_h10.npy"}
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on the host (bounded sample)")
@@ -256,6 +284,7 @@ def main():
         "schedule": None if sched is None else sched.as_tuple(),
         "roofline": roofline,
         "viewshed_roofline": vs_roof,
+        "surrogate": sur,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

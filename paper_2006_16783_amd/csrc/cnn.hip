@@ -96,7 +96,7 @@ __global__ __launch_bounds__(64 * kFwdWaves) void cnn_fwd_kernel(FwdArgs A)
     // per-wave activations: H1 [256 pos][16 ch] bf16, H2 [64 pos][16 ch]
     uint16_t *H1 = reinterpret_cast<uint16_t *>(smem) + wave * (256 * 16 + 64 * 16);
     uint16_t *H2 = H1 + 256 * 16;
-    float *tile = reinterpret_cast<float *>(smem + kFwdWaves * (256 * 16 + 64 * 16) * 2);
+    int16_t *tile = reinterpret_cast<int16_t *>(smem + kFwdWaves * (256 * 16 + 64 * 16) * 2);
 
     // weights as B fragments (bf16) and per-lane biases
     const float *p = A.params;
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(64 * kFwdWaves) void cnn_fwd_kernel(FwdArgs A)
             int64_t gy = ty0 + r, gx = tx0 + c;
             gy = gy < 0 ? 0 : gy > A.nrows - 1 ? A.nrows - 1 : gy;
             gx = gx < 0 ? 0 : gx > A.ncols - 1 ? A.ncols - 1 : gx;
-            tile[e] = (float)A.z[gy * A.ld + gx];
+            tile[e] = A.z[gy * A.ld + gx];
         }
         __syncthreads();
         nloc = A.BL * A.BL;
@@ -160,7 +160,7 @@ __global__ __launch_bounds__(64 * kFwdWaves) void cnn_fwd_kernel(FwdArgs A)
                 int64_t gy = cy - kPatch / 2 + r, gx = cx - kPatch / 2 + lane;
                 gy = gy < 0 ? 0 : gy > A.nrows - 1 ? A.nrows - 1 : gy;
                 gx = gx < 0 ? 0 : gx > A.ncols - 1 ? A.ncols - 1 : gx;
-                tile[r * kPatch + lane] = (float)A.z[gy * A.ld + gx];
+                tile[r * kPatch + lane] = A.z[gy * A.ld + gx];
             }
             wave_lds_sync();
         } else {
@@ -177,8 +177,8 @@ __global__ __launch_bounds__(64 * kFwdWaves) void cnn_fwd_kernel(FwdArgs A)
             for (int e = lane; e < ss; e += 64) {
                 const int r = e / A.stride, c = e - r * A.stride;
                 if (li * A.stride + r < A.nrows && lj * A.stride + c < A.ncols) {
-                    const int v = (int)tile[(py * A.stride + r + kPatch / 2) * tw +
-                                            px * A.stride + c + kPatch / 2];
+                    const int v = tile[(py * A.stride + r + kPatch / 2) * tw +
+                                       px * A.stride + c + kPatch / 2];
                     const int key = ((v + 32768) << 12) | (4095 - e);
                     best = key > best ? key : best;
                 }
@@ -195,16 +195,16 @@ __global__ __launch_bounds__(64 * kFwdWaves) void cnn_fwd_kernel(FwdArgs A)
             or_ = py * A.stride + r;
             oc = px * A.stride + c;
         }
-        const float zc = tile[(or_ + kPatch / 2) * tw + oc + kPatch / 2];
+        const int zc = tile[(or_ + kPatch / 2) * tw + oc + kPatch / 2];
 
         // ---- conv1: one MFMA per output row oy (16 output columns)
 #pragma unroll 4
         for (int oy = 0; oy < 16; oy++) {
-            const float *src = tile + (or_ + 4 * oy + hi) * tw + oc + 4 * lo;
+            const int16_t *src = tile + (or_ + 4 * oy + hi) * tw + oc + 4 * lo;
             // elevation differences in units of 256 m (exact power-of-two scale)
             constexpr float kScale = 0.00390625f;
-            const float v0 = (src[0] - zc) * kScale, v1 = (src[1] - zc) * kScale;
-            const float v2 = (src[2] - zc) * kScale, v3 = (src[3] - zc) * kScale;
+            const float v0 = (float)(src[0] - zc) * kScale, v1 = (float)(src[1] - zc) * kScale;
+            const float v2 = (float)(src[2] - zc) * kScale, v3 = (float)(src[3] - zc) * kScale;
             const s4 a = pack4(v0, v1, v2, v3);
             if (kTrain) {
                 uint16_t *ps = A.Pst + pid * 4096 + (4 * oy + hi) * 64 + 4 * lo;
@@ -232,9 +232,9 @@ __global__ __launch_bounds__(64 * kFwdWaves) void cnn_fwd_kernel(FwdArgs A)
 #pragma unroll
             for (int tap = 0; tap < 9; tap++) {
                 const int ky = tap / 3, kx = tap - ky * 3;
-                const uint16_t *src = H1 + ((2 * oy + ky) * 16 + (2 * ox + kx)) * 16 + 4 * hi;
-                s4 a;
-                a.x = (short)src[0]; a.y = (short)src[1]; a.z = (short)src[2]; a.w = (short)src[3];
+                // 4 consecutive channels: one 8-byte LDS read
+                const s4 a = *reinterpret_cast<const s4 *>(
+                    H1 + ((2 * oy + ky) * 16 + (2 * ox + kx)) * 16 + 4 * hi);
                 c = mfma(a, bw2[tap], c);
             }
 #pragma unroll
@@ -257,9 +257,8 @@ __global__ __launch_bounds__(64 * kFwdWaves) void cnn_fwd_kernel(FwdArgs A)
 #pragma unroll
             for (int tap = 0; tap < 9; tap++) {
                 const int ky = tap / 3, kx = tap - ky * 3;
-                const uint16_t *src = H2 + ((2 * oy + ky) * 7 + (2 * ox + kx)) * 16 + 4 * hi;
-                s4 a;
-                a.x = (short)src[0]; a.y = (short)src[1]; a.z = (short)src[2]; a.w = (short)src[3];
+                const s4 a = *reinterpret_cast<const s4 *>(
+                    H2 + ((2 * oy + ky) * 7 + (2 * ox + kx)) * 16 + 4 * hi);
                 c3[0] = mfma(a, bw3[tap][0], c3[0]);
                 c3[1] = mfma(a, bw3[tap][1], c3[1]);
             }
@@ -653,7 +652,7 @@ extern "C" int siting_cnn_forward(const float *params, const int16_t *z, int64_t
     a.centres = centres; a.nposts = B;
     a.Pst = w.P; a.H1st = w.H1; a.H2st = w.H2; a.H3st = w.H3; a.gst = w.g; a.yst = w.y;
     hipStream_t s = as_stream(stream);
-    const size_t lds = kFwdWaves * ((256 * 16 + 64 * 16) * 2 + kPatch * kPatch * 4);
+    const size_t lds = kFwdWaves * ((256 * 16 + 64 * 16) * 2 + kPatch * kPatch * 2);
     const int64_t grid = std::min<int64_t>((B + kFwdWaves - 1) / kFwdWaves,
                                            (int64_t)device_cus() * 8);
     hipLaunchKernelGGL(cnn_fwd_kernel<true>, dim3((unsigned)grid), dim3(64 * kFwdWaves), lds, s, a);
@@ -798,7 +797,7 @@ extern "C" int siting_cnn_score_terrain(const float *params, const int16_t *z, i
     a.blocks_c = (a.lat_c + a.BL - 1) / a.BL;
     a.score = score;
     const int tw = a.BL * stride + kPatch - 1;
-    const size_t lds = kFwdWaves * (256 * 16 + 64 * 16) * 2 + (size_t)tw * tw * 4;
+    const size_t lds = kFwdWaves * (256 * 16 + 64 * 16) * 2 + (size_t)tw * tw * 2;
     if ((int64_t)lds > device_max_lds()) {
         set_error("%s: tile does not fit in LDS", fn);
         return SITING_E_UNSUPPORTED;

@@ -30,7 +30,7 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=4)
     ap.add_argument("--batch", type=int, default=512)
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--stride", type=int, default=4)
+    ap.add_argument("--stride", type=int, default=8)
     ap.add_argument("--observers", type=int, default=1000)
     ap.add_argument("--quick", action="store_true", help="small smoke configuration")
     ap.add_argument("--save", action="store_true", help="store the trained weights in the package")

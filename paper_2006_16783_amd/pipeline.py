@@ -157,16 +157,21 @@ class _Timer:
 
 
 def run(z, cfg: SitingConfig, key=None, key_stride=1, sched=None, timing=True,
-        ws_cache: dict | None = None) -> SitingResult:
+        surrogate=None) -> SitingResult:
     """One pass of the whole siting path over the device terrain z (int16,
-    resident in HBM).  `key` (float32 device tensor) replaces the VIX count
-    as the FINDMAX ranking when given (surrogate ranking)."""
+    resident in HBM).  The FINDMAX ranking is the VIX count, or `key` (a
+    float32 device tensor) when given, or the CNN score of the cells of a
+    stride grid when surrogate=(params, stride) is given (computed inside the
+    timed pass)."""
     import torch
     nrows, ncols = z.shape
     dev = z.device
     T = _Timer(timing)
-    T.mark("vix" if key is None else "score")
-    if key is None:
+    T.mark("vix" if key is None and surrogate is None else "score")
+    if surrogate is not None:
+        params, key_stride = surrogate
+        key = L.siting_cnn_score_terrain(params, z, key_stride)
+    elif key is None:
         key = L.siting_vix(z, cfg.roi, cfg.h_t, cfg.h_r, cfg.K, cfg.vix_seed)
     T.mark("findmax")
     cand = L.siting_findmax(key, z, cfg.grid, cfg.grid, cfg.k, key_stride=key_stride)
