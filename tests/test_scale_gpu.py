@@ -1,0 +1,151 @@
+"""Parity at the configurations' full sizes, in the launch configuration the
+benchmark uses, on outputs the oracle can compute one by one: VIX on whole
+rows, FINDMAX on sampled blocks (given the device's counts), viewsheds of
+sampled candidates (edge windows included) and the complete SITE selection
+recomputed by the oracle's lazy greedy from the device's bitmaps."""
+import math
+import sys
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print("[scale]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def S():
+    assert torch.cuda.is_available()
+    import paper_2006_16783_amd as S
+    return S
+
+
+def _check_rows(orc, z_host, cnt_dev, cfg, rows):
+    for r in rows:
+        want = orc.vix(z_host, cfg.roi, cfg.h_t, cfg.h_r, cfg.K, cfg.vix_seed, rows=(r, r + 1))[r]
+        got = cnt_dev[r].cpu().numpy()
+        assert (got == want).all(), ("vix row", r, int((got != want).sum()))
+
+
+def _check_blocks(cnt_h, z_host, cand, G, k, blocks):
+    nr, nc = z_host.shape
+    for b in blocks:
+        bi, bj = divmod(b, G)
+        r0, r1 = bi * nr // G, (bi + 1) * nr // G
+        c0, c1 = bj * nc // G, (bj + 1) * nc // G
+        yy, xx = np.mgrid[r0:r1, c0:c1]
+        idx = (yy * nc + xx).ravel()
+        key = cnt_h[r0:r1, c0:c1].ravel().astype(np.int64)
+        zz = z_host[r0:r1, c0:c1].ravel().astype(np.int64)
+        order = np.lexsort((idx, -zz, -key))
+        want = idx[order][:k]
+        assert (cand[b * k:(b + 1) * k] == want).all(), ("findmax block", b)
+
+
+def _check_viewsheds(orc, z_host, obs, off, bm_h, picks):
+    for i in picks:
+        one = orc.viewshed_one(z_host, obs[i]).ravel()
+        assert (bm_h[off[i]:off[i + 1]] == one).all(), ("viewshed", i, obs[i])
+
+
+def _check_site(orc, bm_h, off, obs, nr, nc, max_obs, target, sel, gains):
+    wsel, wgain, _, ev = orc.greedy(bm_h, off, obs, nr, nc, max_obs, target, lazy=True)
+    assert len(wsel) == len(sel)
+    assert (np.asarray(sel) == wsel).all() and (np.asarray(gains) == wgain).all()
+
+
+def _edge_picks(obs, nr, nc, n, rng):
+    R = obs["roi"].astype(np.int64)
+    edge = np.nonzero((obs["x"] < R) | (obs["y"] < R) | (obs["x"] >= nc - R) | (obs["y"] >= nr - R))[0]
+    picks = list(edge[:n // 4]) + list(rng.choice(len(obs), n - min(len(edge), n // 4), replace=False))
+    return sorted(set(int(p) for p in picks))
+
+
+def test_full_scale_46400(S, orc):
+    from paper_2006_16783_amd import pipeline as P
+    from synth import fbm_torch
+    cfg = P.CONFIGS["full_46400"]
+    t0 = time.time()
+    z = fbm_torch(cfg.n, cfg.beta, cfg.zmax, cfg.seed, device="cuda")
+    torch.cuda.synchronize()
+    _say("terrain", time.time() - t0)
+    res = P.run(z, cfg)
+    _say("pipeline", res.stage_ms)
+    cnt = S.siting_vix(z, cfg.roi, cfg.h_t, cfg.h_r, cfg.K, cfg.vix_seed)
+    z_host = z.cpu().numpy()
+    _check_rows(orc, z_host, cnt, cfg, [0, 17, cfg.n // 2, cfg.n - 1])
+    _say("vix rows ok")
+    cnt_h = cnt.cpu().numpy()
+    G, k = cfg.grid, cfg.k
+    cand = S.siting_findmax(cnt, z, G, G, k).cpu().numpy()
+    assert (cand >= 0).all() and len(cand) == G * G * k
+    _check_blocks(cnt_h, z_host, cand, G, k, [0, G - 1, G * G - 1, G * (G - 1), 2017, 3000])
+    assert (cand == res.candidates).all()
+    _say("findmax ok")
+    del cnt, cnt_h
+    obs, off = res.observers, res.offsets
+    bm = S.siting_viewshed_batch(z, S.observers_to_device(obs), torch.from_numpy(off).cuda(), cfg.roi)
+    bm_h = bm.cpu().numpy().view(np.uint64)
+    rng = np.random.default_rng(0)
+    _check_viewsheds(orc, z_host, obs, off, bm_h, _edge_picks(obs, cfg.n, cfg.n, 96, rng))
+    _say("viewsheds ok")
+    _check_site(orc, bm_h, off, obs, cfg.n, cfg.n, cfg.max_obs,
+                P.target_cells(cfg.target_frac, cfg.n, cfg.n), res.selected, res.gains)
+    _say("site ok", len(res.selected), time.time() - t0)
+
+
+def test_batched_4096_r200(S, orc):
+    # 4096^2 (0-2000 m), ROI 200, VIX with 50 receivers, 50x50 blocks x 4 =
+    # 10,000 tentative observers in one persistent launch, SITE to 2000 or 90%
+    from paper_2006_16783_amd import pipeline as P
+    from synth import fbm_torch
+    cfg = P.CONFIGS["batched_4096"]
+    z = fbm_torch(cfg.n, cfg.beta, cfg.zmax, cfg.seed, device="cuda")
+    res = P.run(z, cfg)
+    _say("batched pipeline", res.stage_ms, len(res.observers), len(res.selected))
+    assert len(res.observers) == 10000
+    z_host = z.cpu().numpy()
+    cnt = S.siting_vix(z, cfg.roi, cfg.h_t, cfg.h_r, cfg.K, cfg.vix_seed)
+    _check_rows(orc, z_host, cnt, cfg, [0, 1000, cfg.n - 1])
+    obs, off = res.observers, res.offsets
+    bm = S.siting_viewshed_batch(z, S.observers_to_device(obs), torch.from_numpy(off).cuda(), cfg.roi)
+    bm_h = bm.cpu().numpy().view(np.uint64)
+    _check_viewsheds(orc, z_host, obs, off, bm_h,
+                     _edge_picks(obs, cfg.n, cfg.n, 64, np.random.default_rng(1)))
+    _check_site(orc, bm_h, off, obs, cfg.n, cfg.n, cfg.max_obs,
+                P.target_cells(cfg.target_frac, cfg.n, cfg.n), res.selected, res.gains)
+    _say("batched ok")
+
+
+def test_uneven_16384_autotuned(S, orc):
+    # 16384^2 (exponent 2.2, 0-3000 m); 40,000 candidates with ROI drawn from
+    # 50-400 and height from 5-100 m, edge windows forced; autotuned schedule;
+    # SITE to 4000
+    from paper_2006_16783_amd import pipeline as P
+    from synth import fbm_torch, uniform_observers
+    n = 16384
+    z = fbm_torch(n, 2.2, 3000, 1, device="cuda")
+    obs = uniform_observers(n, n, 40000, 7, roi=(50, 400), height=(5, 100))
+    off = S.siting_viewshed_layout(obs, n, n)
+    obs_d = S.observers_to_device(obs)
+    off_d = torch.from_numpy(off).cuda()
+    order_d = torch.from_numpy(S.siting_viewshed_order(obs)).cuda()
+    bm = torch.empty(int(off[-1]), dtype=torch.int64, device="cuda")
+    best, times = S.siting_autotune(z, obs_d, off_d, 400, bm, order_dev=order_d)
+    _say("autotune", best, [round(t, 2) for t in times])
+    bm = S.siting_viewshed_batch(z, obs_d, off_d, 400, order_dev=order_d, sched=best, bitmaps=bm)
+    sel, gains, nsel, _ = S.siting_greedy(bm, off_d, obs_d, n, n, 4000, n * n)
+    m = int(nsel.item())
+    z_host = z.cpu().numpy()
+    bm_h = bm.cpu().numpy().view(np.uint64)
+    _check_viewsheds(orc, z_host, obs, off, bm_h, _edge_picks(obs, n, n, 64, np.random.default_rng(2)))
+    _say("uneven viewsheds ok")
+    _check_site(orc, bm_h, off, obs, n, n, 4000, n * n, sel[:m].cpu().numpy(),
+                gains[:m].cpu().numpy())
+    _say("uneven ok", m)
