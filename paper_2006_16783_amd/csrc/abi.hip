@@ -69,7 +69,7 @@ int device_cus()
 int device_max_lds()
 {
     int l = props().lds;
-    return l > 0 ? l : 65536;
+    return l > 0 ? l : 160 * 1024;  // gfx950 without a device to ask (host-only use)
 }
 
 }  // namespace siting

@@ -27,7 +27,13 @@ extern "C" int siting_autotune_candidates(int32_t rmax, siting_schedule *out_hos
     SITING_REQUIRE(max_out >= 0 && (max_out == 0 || out_host), "siting_autotune_candidates: bad output");
     const int budget = std::min(160 * 1024, device_max_lds());
     std::vector<siting_schedule> c;
-    for (int stage : {rmax, 0}) {
+    // stage everything, nothing, or only the observers up to a partial ROI
+    // (uneven batches: small observers from LDS, large ones through L2)
+    std::vector<int> stages{rmax, 0};
+    for (int st : {64, 100, 128, 160, 200, 256})
+        if (st < rmax)
+            stages.push_back(st);
+    for (int stage : stages) {
         int lds = viewshed_lds_bytes(rmax, stage);
         if (lds > budget)
             continue;

@@ -14,7 +14,9 @@
 // posts; it first draws the receivers of the batch into a queue in LDS, then
 // its lanes pull tests from the queue, and a lane whose test ends takes the
 // next one (ballot + prefix count), so lanes stay busy until the queue drains.
-// Visible results are accumulated per post with LDS atomics.
+// Visible results are accumulated per post with LDS atomics.  Each queue
+// iteration advances a test by a block of steps whose reads are all issued
+// before any comparison, one LDS round trip per block.
 //
 // Draws: post t owns one Philox4x64-10 stream (word a = word a%4 of the
 // block {t, a/4, 0, 0} under key {seed, 0}); the generator runs only when some
@@ -241,28 +243,47 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
                 cursor += __popcll(m);
                 if (!__any(active) && cursor >= total)
                     break;
+                if (active) {
+                    // kSPI steps at once: addresses first, then every read
+                    // (masked past the end of the LOS), then the comparisons,
+                    // so the step loop waits for LDS once per block of steps
+                    int so[kSPI], sr[kSPI], sa[kSPI], sb[kSPI];
 #pragma unroll
-                for (int sp = 0; sp < kSPI; sp++) {
-                    if (active) {
-                        if (kCount)
-                            steps++;
+                    for (int sp = 0; sp < kSPI; sp++) {
                         r += mn;
                         off += smaj;
                         if (r >= n) {
                             r -= n;
                             off += smin;
                         }
-                        const int z0 = zb[off];
-                        const int z1 = zb[off + smin];  // in the observer-target box
-                        const int S = mul_i24(z0, n) + mul_i24(z1 - z0, r);
-                        rhs += dz;
-                        k--;
-                        const bool blocked = S > rhs;
-                        if (blocked || k == 0) {
-                            if (!blocked)
-                                atomicAdd(&cnt[pl], 1u);
-                            active = false;
+                        so[sp] = off;
+                        sr[sp] = r;
+                    }
+#pragma unroll
+                    for (int sp = 0; sp < kSPI; sp++) {
+                        sa[sp] = 0;
+                        sb[sp] = 0;
+                        if (sp < k) {
+                            sa[sp] = zb[so[sp]];
+                            sb[sp] = zb[so[sp] + smin];  // in the observer-target box
                         }
+                    }
+                    int first = kSPI;  // first blocking step of the block
+#pragma unroll
+                    for (int sp = 0; sp < kSPI; sp++) {
+                        rhs += dz;
+                        const int S = mul_i24(sa[sp], n) + mul_i24(sb[sp] - sa[sp], sr[sp]);
+                        if (sp < k && S > rhs && first == kSPI)
+                            first = sp;
+                    }
+                    const bool blocked = first < kSPI;
+                    if (kCount)
+                        steps += blocked ? first + 1 : (k < kSPI ? k : kSPI);
+                    k -= kSPI;
+                    if (blocked || k <= 0) {
+                        if (!blocked)
+                            atomicAdd(&cnt[pl], 1u);
+                        active = false;
                     }
                 }
             }
@@ -345,8 +366,8 @@ static int vix_launch(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld
     }
     static const int spi = [] {
         const char *e = getenv("SITING_VIX_STEPS_PER_ITER");
-        int v = e ? atoi(e) : 4;
-        return v == 1 ? 1 : v == 2 ? 2 : 4;
+        int v = e ? atoi(e) : 8;
+        return v == 2 ? 2 : v == 4 ? 4 : 8;
     }();
 #define VIX_LAUNCH(LDS, CNT, SPI)                                                              \
     hipLaunchKernelGGL((vix_kernel<LDS, CNT, SPI>), dim3((unsigned)grid), dim3(kVixThreads),   \
@@ -354,10 +375,10 @@ static int vix_launch(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld
                        tiles_c, per_xcd, tile_bytes, stats)
 #define VIX_SPI(LDS, CNT)                    \
     do {                                     \
-        if (spi == 1)                        \
-            VIX_LAUNCH(LDS, CNT, 1);         \
-        else if (spi == 2)                   \
+        if (spi == 2)                        \
             VIX_LAUNCH(LDS, CNT, 2);         \
+        else if (spi == 8)                   \
+            VIX_LAUNCH(LDS, CNT, 8);         \
         else                                 \
             VIX_LAUNCH(LDS, CNT, 4);         \
     } while (0)
