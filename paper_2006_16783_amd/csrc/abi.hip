@@ -72,6 +72,31 @@ int device_max_lds()
     return l > 0 ? l : 160 * 1024;  // gfx950 without a device to ask (host-only use)
 }
 
+int kernel_max_dynamic_lds(const void *kernel)
+{
+    static std::mutex mu;
+    static std::vector<std::pair<const void *, int>> cache;
+    int stat = -1;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        for (auto &e : cache)
+            if (e.first == kernel)
+                stat = e.second;
+    }
+    if (stat < 0) {
+        hipFuncAttributes a{};
+        if (hipFuncGetAttributes(&a, kernel) == hipSuccess) {
+            stat = (int)a.sharedSizeBytes;
+            std::lock_guard<std::mutex> lk(mu);
+            cache.emplace_back(kernel, stat);
+        } else {
+            (void)hipGetLastError();
+            stat = 1024;  // no device to ask: a conservative reserve
+        }
+    }
+    return device_max_lds() - ((stat + 15) & ~15);
+}
+
 }  // namespace siting
 
 using namespace siting;

@@ -15,6 +15,7 @@ int viewshed_launch(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
                     uint64_t *bitmaps, uint32_t *visible, uint32_t *cells, void *ws,
                     hipStream_t s);
 int viewshed_lds_bytes(int32_t rmax, int32_t stage_rmax);
+int viewshed_max_dynamic_lds();
 int validate_schedule(const siting_schedule &sc, const char *fn);
 }  // namespace siting
 
@@ -25,7 +26,7 @@ extern "C" int siting_autotune_candidates(int32_t rmax, siting_schedule *out_hos
     clear_error();
     SITING_REQUIRE(rmax >= 1 && rmax <= kMaxRoi, "siting_autotune_candidates: bad rmax");
     SITING_REQUIRE(max_out >= 0 && (max_out == 0 || out_host), "siting_autotune_candidates: bad output");
-    const int budget = std::min(160 * 1024, device_max_lds());
+    const int budget = std::min(160 * 1024, viewshed_max_dynamic_lds());
     std::vector<siting_schedule> c;
     // stage everything, nothing, or only the observers up to a partial ROI
     // (uneven batches: small observers from LDS, large ones through L2)

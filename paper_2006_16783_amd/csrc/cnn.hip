@@ -798,7 +798,7 @@ extern "C" int siting_cnn_score_terrain(const float *params, const int16_t *z, i
     a.score = score;
     const int tw = a.BL * stride + kPatch - 1;
     const size_t lds = kFwdWaves * (256 * 16 + 64 * 16) * 2 + (size_t)tw * tw * 2;
-    if ((int64_t)lds > device_max_lds()) {
+    if ((int64_t)lds > kernel_max_dynamic_lds(reinterpret_cast<const void *>(&cnn_fwd_kernel<false>))) {
         set_error("%s: tile does not fit in LDS", fn);
         return SITING_E_UNSUPPORTED;
     }

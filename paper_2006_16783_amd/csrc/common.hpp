@@ -41,6 +41,10 @@ int check_launch(const char *what);
 // Compute units and maximum LDS bytes per workgroup of the current device.
 int device_cus();
 int device_max_lds();
+// Dynamic LDS bytes a launch of `kernel` may request: the device maximum less
+// the kernel's static __shared__ variables (the two together must fit, and
+// the runtime does not reject a launch that exceeds it).
+int kernel_max_dynamic_lds(const void *kernel);
 
 inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 

@@ -319,7 +319,8 @@ extern "C" int siting_greedy(const uint64_t *bitmaps, const int64_t *offsets,
         return SITING_E_WORKSPACE;
     }
     const int64_t nblocks = (n + kGreedyBlock - 1) / kGreedyBlock;
-    if (nblocks > kGreedyMaxBlocks || nblocks * 8 + 256 > device_max_lds()) {
+    if (nblocks > kGreedyMaxBlocks ||
+        nblocks * 8 > kernel_max_dynamic_lds(reinterpret_cast<const void *>(&greedy_run))) {
         set_error("%s: %lld candidates exceed the supported maximum", fn, (long long)n);
         return SITING_E_UNSUPPORTED;
     }

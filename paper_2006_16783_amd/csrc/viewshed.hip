@@ -401,6 +401,11 @@ int lds_bytes_for(int rmax, int stage_rmax)
 
 }  // namespace
 
+int viewshed_max_dynamic_lds()
+{
+    return kernel_max_dynamic_lds(reinterpret_cast<const void *>(&viewshed_kernel));
+}
+
 int viewshed_launch(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
                     const siting_observer *obs, int64_t n, const int64_t *offsets,
                     const int32_t *order, int32_t rmax, const siting_schedule &sc, int32_t sink,
@@ -409,9 +414,9 @@ int viewshed_launch(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
 {
     int stage = std::min(sc.stage_rmax, rmax);
     int lds = lds_bytes_for(rmax, stage);
-    if (lds > device_max_lds()) {
-        set_error("siting_viewshed_batch: schedule needs %d bytes of LDS (device max %d)", lds,
-                  device_max_lds());
+    if (lds > viewshed_max_dynamic_lds()) {
+        set_error("siting_viewshed_batch: schedule needs %d bytes of LDS (at most %d)", lds,
+                  viewshed_max_dynamic_lds());
         return SITING_E_UNSUPPORTED;
     }
     int64_t grid = (int64_t)device_cus() * sc.groups_per_cu;
@@ -436,7 +441,7 @@ int viewshed_default_schedule(int32_t rmax, siting_schedule *sc)
     sc->reserved = 0;
     sc->waves = 4;
     int lds_staged = lds_bytes_for(rmax, rmax);
-    if (rmax <= 160 && lds_staged <= std::min(budget, device_max_lds())) {
+    if (rmax <= 160 && lds_staged <= std::min(budget, viewshed_max_dynamic_lds())) {
         sc->stage_rmax = rmax;
         sc->groups_per_cu = std::max(1, std::min(8, budget / lds_staged));
     } else {

@@ -11,12 +11,18 @@
 // lengths vary from 1 to R steps (7 on average on rough terrain, while the
 // visible ones run to the end).  One test per lane would leave a wavefront
 // waiting for its longest test.  Instead each wavefront takes batches of 64
-// posts; it first draws the receivers of the batch into a queue in LDS, then
-// its lanes pull tests from the queue, and a lane whose test ends takes the
-// next one (ballot + prefix count), so lanes stay busy until the queue drains.
-// Visible results are accumulated per post with LDS atomics.  Each queue
-// iteration advances a test by a block of steps whose reads are all issued
-// before any comparison, one LDS round trip per block.
+// posts of its tile; it draws up to 10 receivers per post into registers of
+// the post's lane (the queue: row j holds draw j of every post), then its
+// lanes pull tests from the queue in order, reading the entry and the post's
+// offset and eye elevation from the owning lane (ds_bpermute), and a lane
+// whose test ends takes the next one (ballot + prefix count).  When the queue
+// runs dry the wavefront draws its next chunk or claims its next batch at
+// once, while the long tests of the previous batch keep running; visible
+// results go to per-post LDS counters, double-buffered by batch, so a batch's
+// counts are written out once its last test has ended.  A wavefront drains
+// only at the end of its tile.  Each queue iteration advances a test by a
+// block of steps whose reads are all issued before any comparison, one LDS
+// round trip per block.
 //
 // Draws: post t owns one Philox4x64-10 stream (word a = word a%4 of the
 // block {t, a/4, 0, 0} under key {seed, 0}); the generator runs only when some
@@ -34,16 +40,16 @@
 namespace siting {
 namespace {
 
-constexpr int kVixWaves = 8;
+constexpr int kVixWaves = 16;
 constexpr int kVixThreads = 64 * kVixWaves;
 constexpr int kVixChunk = 10;          // draws per post per queue round
 constexpr int kVixMaxAttempts = 64;    // consecutive rejections before a draw fails
 constexpr int kVixMaxRoi = 4094;       // queue entries hold dx, dy in 13 bits
 constexpr uint32_t kSkip = 0xFFFFFFFFu;
 
-// LDS bytes besides the tile: per wavefront a queue of 64 x kVixChunk tests
-// and per-post offset, eye height and visible count.
-constexpr int kVixWaveLds = 64 * (kVixChunk * 4 + 12);
+// LDS bytes besides the tile: per wavefront the visible counts of its two
+// batches in flight.
+constexpr int kVixWaveLds = 2 * 64 * 4;
 
 // Full 128-bit product of two 64-bit words from four 32x32->64 multiply-adds
 // (schoolbook, carries folded into the adds).
@@ -86,9 +92,14 @@ __device__ __forceinline__ int mul_i24(int a, int b)
     return r;
 }
 
-__device__ __forceinline__ uint32_t pack_test(int lane, int dx, int dy)
+__device__ __forceinline__ uint32_t pack_test(int dx, int dy)
 {
-    return ((uint32_t)lane << 26) | ((uint32_t)(dx + 4096) << 13) | (uint32_t)(dy + 4096);
+    return ((uint32_t)(dx + 4096) << 13) | (uint32_t)(dy + 4096);
+}
+
+__device__ __forceinline__ uint32_t lane_read(int src, uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)v);
 }
 
 // kLds: terrain tile staged in LDS (else global reads).  kCount: also count
@@ -112,13 +123,12 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
     const int pitch = T + 2 * R;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int16_t *tile = reinterpret_cast<int16_t *>(smem);
-    uint32_t *q = reinterpret_cast<uint32_t *>(smem + tile_bytes) + wave * 64 * kVixChunk;
-    int32_t *pofs = reinterpret_cast<int32_t *>(smem + tile_bytes) +
-                    kVixWaves * 64 * kVixChunk + wave * 64;
-    int32_t *pE = pofs + kVixWaves * 64;
-    uint32_t *cnt = reinterpret_cast<uint32_t *>(pE + kVixWaves * 64);
+    // visible counts of this wavefront's two batches in flight
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(smem + tile_bytes) + wave * 128;
     if (tid == 0)
         s_batch = 0;
+    cnt[lane] = 0;
+    cnt[64 + lane] = 0;
     if (kLds) {
         const int64_t oy = r0 - R, ox = c0 - R;
         const int64_t gy0 = oy < 0 ? 0 : oy, gy1 = r0 + T + R > nrows ? nrows : r0 + T + R;
@@ -141,156 +151,241 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
     const int nposts = T * T, nbatch = (nposts + 63) >> 6;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
-    for (;;) {
+    auto claim = [&]() {
         int bt = 0;
         if (lane == 0)
             bt = atomicAdd(&s_batch, 1);
-        bt = __shfl(bt, 0, 64);
-        if (bt >= nbatch)
-            break;
+        return __shfl(bt, 0, 64);
+    };
+
+    // ---- the batch being queued: this lane's post and its receiver stream
+    int buf = 0;                  // count buffer of the batch being queued
+    bool valid = false;
+    uint64_t t = 0;               // post index = stream counter
+    int po = 0, Epost = 0;        // post offset from zb, eye elevation
+    int bxo = 0, byo = 0;         // clipped box corner relative to the post
+    uint32_t wx = 0, wy = 0;      // clipped box extent
+    uint64_t blk_next = 0, w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+    int nbuf = 0;
+    // the previous batch, whose tests may still run
+    bool prev_pending = false, prev_valid = false;
+    uint64_t prev_t = 0;
+    // queue of the current chunk: row j of the queue is draw j0+j of every
+    // lane's post; e[0] holds row (cursor >> 6) of this lane's post
+    uint32_t e[kVixChunk];
+    int j0 = 0, kc = 0, cursor = 0, total = 0;
+
+    auto setup = [&](int bt) {
         const int p = bt * 64 + lane;
         const int py = p / T, px = p - py * T;
-        const bool valid = p < nposts && py < tile_rows && px < tile_cols;
+        valid = p < nposts && py < tile_rows && px < tile_cols;
         const int64_t y = r0 + py, x = c0 + px;
-        const int po = kLds ? (py + R) * pitch + (px + R) : py * (int)ld + px;
-        const int Epost = valid ? (int)zb[po] + h_t : 0;
-        pofs[lane] = po;
-        pE[lane] = Epost;
-        cnt[lane] = 0;
-        // this post's receiver stream
-        const uint64_t t = (uint64_t)(y * ncols + x);
+        po = kLds ? (py + R) * pitch + (px + R) : py * (int)ld + px;
+        Epost = valid ? (int)zb[po] + h_t : 0;
+        t = (uint64_t)(y * ncols + x);
         const int64_t bx0 = x - R < 0 ? 0 : x - R, bx1 = x + R > ncols - 1 ? ncols - 1 : x + R;
         const int64_t by0 = y - R < 0 ? 0 : y - R, by1 = y + R > nrows - 1 ? nrows - 1 : y + R;
-        const uint64_t wx = (uint64_t)(bx1 - bx0 + 1), wy = (uint64_t)(by1 - by0 + 1);
-        uint64_t blk_next = 0, w0 = 0, w1 = 0, w2 = 0, w3 = 0;
-        int nbuf = 0;
-        for (int j0 = 0; j0 < K; j0 += kVixChunk) {
-            const int kc = K - j0 < kVixChunk ? K - j0 : kVixChunk;
-            // ---- draw kc receivers per post into the queue
-            const int need = valid ? kc : 0;
-            int made = 0, att = 0;
-            for (int j = need; j < kc; j++)
-                q[j * 64 + lane] = kSkip;
-            while (__any(made < need)) {
-                const bool want = made < need && nbuf == 0;
-                if (__any(want)) {
-                    uint64_t o[4];
-                    philox4x64_10(t, blk_next, 0, 0, seed, 0, o);
-                    if (want) {
-                        w0 = o[0]; w1 = o[1]; w2 = o[2]; w3 = o[3];
-                        blk_next++;
-                        nbuf = 4;
-                    }
-                }
+        bxo = (int)(bx0 - x);
+        byo = (int)(by0 - y);
+        wx = (uint32_t)(bx1 - bx0 + 1);
+        wy = (uint32_t)(by1 - by0 + 1);
+        blk_next = 0;
+        nbuf = 0;
+        j0 = 0;
+    };
+
+    // draws j0 .. j0+kc-1 of every valid lane's post into e[]
+    auto generate = [&]() {
+        kc = K - j0 < kVixChunk ? K - j0 : kVixChunk;
+        const int need = valid ? kc : 0;
 #pragma unroll
-                for (int i = 0; i < 4; i++) {
-                    if (made < need && nbuf > 0) {
-                        const uint64_t u = nbuf == 4 ? w0 : nbuf == 3 ? w1 : nbuf == 2 ? w2 : w3;
-                        nbuf--;
-                        att++;
-                        // ((u >> 32) * wx) >> 32, i.e. the high word of a 32x32 product
-                        const int dx = (int)(bx0 - x) + (int)__umulhi((uint32_t)(u >> 32), (uint32_t)wx);
-                        const int dy = (int)(by0 - y) + (int)__umulhi((uint32_t)u, (uint32_t)wy);
-                        const bool ok = (dx | dy) != 0 && dx * dx + dy * dy <= R2;
-                        if (ok || att == kVixMaxAttempts) {
-                            q[made * 64 + lane] = ok ? pack_test(lane, dx, dy) : kSkip;
-                            made++;
-                            att = 0;
-                            if (kCount && ok)
-                                tests++;
-                        }
-                    }
+        for (int j = 0; j < kVixChunk; j++)
+            e[j] = kSkip;
+        int made = 0, att = 0;
+        while (__any(made < need)) {
+            const bool want = made < need && nbuf == 0;
+            if (__any(want)) {
+                uint64_t o[4];
+                philox4x64_10(t, blk_next, 0, 0, seed, 0, o);
+                if (want) {
+                    w0 = o[0]; w1 = o[1]; w2 = o[2]; w3 = o[3];
+                    blk_next++;
+                    nbuf = 4;
                 }
             }
-            // ---- run the queued tests, refilling idle lanes
-            const int total = kc * 64;
-            int cursor = 0;
-            bool active = false;
-            int n = 0, mn = 0, r = 0, off = 0, smaj = 0, smin = 0, rhs = 0, dz = 0, k = 0, pl = 0;
-            for (;;) {
-                const bool idle = !active;
-                const uint64_t m = __ballot(idle);
-                if (idle) {
-                    const int idx = cursor + __popcll(m & lt_mask);
-                    if (idx < total) {
-                        const uint32_t e = q[idx];
-                        if (e != kSkip) {
-                            pl = (int)(e >> 26);
-                            const int dx = (int)((e >> 13) & 0x1FFF) - 4096;
-                            const int dy = (int)(e & 0x1FFF) - 4096;
-                            const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
-                            const bool xmaj = adx >= ady;
-                            n = xmaj ? adx : ady;
-                            if (n <= 1) {
-                                atomicAdd(&cnt[pl], 1u);  // adjacent: always visible
-                            } else {
-                                const int sx = dx < 0 ? -1 : 1, sy = dy < 0 ? -rs : rs;
-                                mn = xmaj ? ady : adx;
-                                smaj = xmaj ? sx : sy;
-                                smin = xmaj ? sy : sx;
-                                off = pofs[pl];
-                                const int E = pE[pl];
-                                const int Zt = (int)zb[off + (kLds ? mul_i24(dy, rs) : dy * rs) + dx] + h_r;
-                                rhs = E * n;
-                                dz = Zt - E;
-                                r = 0;
-                                k = n - 1;  // steps left
-                                active = true;
-                            }
-                        }
-                    }
-                }
-                cursor += __popcll(m);
-                if (!__any(active) && cursor >= total)
-                    break;
-                if (active) {
-                    // kSPI steps at once: addresses first, then every read
-                    // (masked past the end of the LOS), then the comparisons,
-                    // so the step loop waits for LDS once per block of steps
-                    int so[kSPI], sr[kSPI], sa[kSPI], sb[kSPI];
 #pragma unroll
-                    for (int sp = 0; sp < kSPI; sp++) {
-                        r += mn;
-                        off += smaj;
-                        if (r >= n) {
-                            r -= n;
-                            off += smin;
-                        }
-                        so[sp] = off;
-                        sr[sp] = r;
-                    }
+            for (int i = 0; i < 4; i++) {
+                if (made < need && nbuf > 0) {
+                    const uint64_t u = nbuf == 4 ? w0 : nbuf == 3 ? w1 : nbuf == 2 ? w2 : w3;
+                    nbuf--;
+                    att++;
+                    // ((u >> 32) * wx) >> 32, i.e. the high word of a 32x32 product
+                    const int dx = bxo + (int)__umulhi((uint32_t)(u >> 32), wx);
+                    const int dy = byo + (int)__umulhi((uint32_t)u, wy);
+                    const bool ok = (dx | dy) != 0 && dx * dx + dy * dy <= R2;
+                    if (ok || att == kVixMaxAttempts) {
+                        // append: shift the lane's queue down one row
 #pragma unroll
-                    for (int sp = 0; sp < kSPI; sp++) {
-                        sa[sp] = 0;
-                        sb[sp] = 0;
-                        if (sp < k) {
-                            sa[sp] = zb[so[sp]];
-                            sb[sp] = zb[so[sp] + smin];  // in the observer-target box
-                        }
-                    }
-                    int first = kSPI;  // first blocking step of the block
-#pragma unroll
-                    for (int sp = 0; sp < kSPI; sp++) {
-                        rhs += dz;
-                        const int S = mul_i24(sa[sp], n) + mul_i24(sb[sp] - sa[sp], sr[sp]);
-                        if (sp < k && S > rhs && first == kSPI)
-                            first = sp;
-                    }
-                    const bool blocked = first < kSPI;
-                    if (kCount)
-                        steps += blocked ? first + 1 : (k < kSPI ? k : kSPI);
-                    k -= kSPI;
-                    if (blocked || k <= 0) {
-                        if (!blocked)
-                            atomicAdd(&cnt[pl], 1u);
-                        active = false;
+                        for (int j = 0; j + 1 < kVixChunk; j++)
+                            e[j] = e[j + 1];
+                        e[kVixChunk - 1] = ok ? pack_test(dx, dy) : kSkip;
+                        made++;
+                        att = 0;
+                        if (kCount && ok)
+                            tests++;
                     }
                 }
             }
         }
-        if (valid)
-            count[t] = (uint8_t)cnt[lane];
+        // rows 0..kc-1 to e[0..kc-1]
+        for (int s = kc; s < kVixChunk; s++) {
+#pragma unroll
+            for (int j = 0; j + 1 < kVixChunk; j++)
+                e[j] = e[j + 1];
+        }
+        cursor = 0;
+        total = kc * 64;
+    };
+
+    auto retire = [&](int bf, bool v, uint64_t tt) {
+        if (v)
+            count[tt] = (uint8_t)cnt[bf * 64 + lane];
+        cnt[bf * 64 + lane] = 0;
+    };
+
+    {
+        const int bt = claim();
+        if (bt >= nbatch)
+            return;
+        setup(bt);
+        generate();
     }
+    bool more = true;  // further batches may remain in the tile
+    bool active = false;
+    int n = 0, mn = 0, r = 0, off = 0, smaj = 0, smin = 0, rhs = 0, dz = 0, k = 0, pl = 0;
+    for (;;) {
+        if (cursor >= total) {
+            // queue drained: next chunk of this batch, or the next batch
+            // once no test of the batch before this one is running
+            if (j0 + kc < K) {
+                j0 += kc;
+                generate();
+            } else if (more) {
+                bool can = true;
+                if (prev_pending) {
+                    if (__any(active && (pl >> 6) != buf)) {
+                        can = false;
+                    } else {
+                        retire(buf ^ 1, prev_valid, prev_t);
+                        prev_pending = false;
+                    }
+                }
+                if (can) {
+                    const int bt = claim();
+                    if (bt >= nbatch) {
+                        more = false;
+                    } else {
+                        prev_pending = true;
+                        prev_valid = valid;
+                        prev_t = t;
+                        buf ^= 1;
+                        setup(bt);
+                        generate();
+                    }
+                }
+            }
+            if (cursor >= total && !more && !__any(active))
+                break;
+        }
+        if (cursor < total) {
+            // idle lanes take the next tests of the queue, in order
+            const bool idle = !active;
+            const uint64_t m = __ballot(idle);
+            const int idx = cursor + __popcll(m & lt_mask);
+            const int src = idx & 63;
+            const uint32_t v0 = lane_read(src, e[0]), v1 = lane_read(src, e[1]);
+            const int spo = (int)lane_read(src, (uint32_t)po);
+            const int sE = (int)lane_read(src, (uint32_t)Epost);
+            const uint32_t ent = (idx >> 6) == (cursor >> 6) ? v0 : v1;
+            if (idle && idx < total && ent != kSkip) {
+                const int dx = (int)((ent >> 13) & 0x1FFF) - 4096;
+                const int dy = (int)(ent & 0x1FFF) - 4096;
+                const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
+                const bool xmaj = adx >= ady;
+                const int cidx = buf * 64 + src;
+                n = xmaj ? adx : ady;
+                if (n <= 1) {
+                    atomicAdd(&cnt[cidx], 1u);  // adjacent: always visible
+                } else {
+                    const int sx = dx < 0 ? -1 : 1, sy = dy < 0 ? -rs : rs;
+                    mn = xmaj ? ady : adx;
+                    smaj = xmaj ? sx : sy;
+                    smin = xmaj ? sy : sx;
+                    off = spo;
+                    const int Zt = (int)zb[spo + (kLds ? mul_i24(dy, rs) : dy * rs) + dx] + h_r;
+                    rhs = sE * n;
+                    dz = Zt - sE;
+                    r = 0;
+                    k = n - 1;  // steps left
+                    pl = cidx;
+                    active = true;
+                }
+            }
+            const int c1 = cursor + __popcll(m);
+            if ((c1 >> 6) != (cursor >> 6)) {
+#pragma unroll
+                for (int j = 0; j + 1 < kVixChunk; j++)
+                    e[j] = e[j + 1];
+            }
+            cursor = c1;
+        }
+        if (active) {
+            // kSPI steps at once: addresses first, then every read (masked
+            // past the end of the LOS), then the comparisons, so the step
+            // loop waits for LDS once per block of steps
+            int so[kSPI], sr[kSPI], sa[kSPI], sb[kSPI];
+#pragma unroll
+            for (int sp = 0; sp < kSPI; sp++) {
+                r += mn;
+                off += smaj;
+                if (r >= n) {
+                    r -= n;
+                    off += smin;
+                }
+                so[sp] = off;
+                sr[sp] = r;
+            }
+#pragma unroll
+            for (int sp = 0; sp < kSPI; sp++) {
+                sa[sp] = 0;
+                sb[sp] = 0;
+                if (sp < k) {
+                    sa[sp] = zb[so[sp]];
+                    sb[sp] = zb[so[sp] + smin];  // in the observer-target box
+                }
+            }
+            int first = kSPI;  // first blocking step of the block
+#pragma unroll
+            for (int sp = 0; sp < kSPI; sp++) {
+                rhs += dz;
+                const int S = mul_i24(sa[sp], n) + mul_i24(sb[sp] - sa[sp], sr[sp]);
+                if (sp < k && S > rhs && first == kSPI)
+                    first = sp;
+            }
+            const bool blocked = first < kSPI;
+            if (kCount)
+                steps += blocked ? first + 1 : (k < kSPI ? k : kSPI);
+            k -= kSPI;
+            if (blocked || k <= 0) {
+                if (!blocked)
+                    atomicAdd(&cnt[pl], 1u);
+                active = false;
+            }
+        }
+    }
+    retire(buf, valid, t);
+    if (prev_pending)
+        retire(buf ^ 1, prev_valid, prev_t);
     if (kCount) {
         atomicAdd(&stats[0], (unsigned long long)steps);
         atomicAdd(&stats[1], (unsigned long long)tests);
@@ -330,7 +425,8 @@ static int vix_launch(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld
     }
     // Largest tile side (multiple of 8, <= 128) whose haloed tile and the
     // wavefront queues fit in LDS.
-    const int lds_max = device_max_lds();
+    // (every instantiation declares the same static LDS)
+    const int lds_max = kernel_max_dynamic_lds(reinterpret_cast<const void *>(&vix_kernel<true, false, 8>));
     const int queue_bytes = kVixWaves * kVixWaveLds;
     int T = 0;
     for (int c = 128; c >= 16; c -= 8) {

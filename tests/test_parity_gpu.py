@@ -39,6 +39,7 @@ def _u64(t):
     ((130, 517), 7, 0, 0, 255, 99),      # K at its maximum, zero heights
     ((64, 64), 100, 10, 10, 10, 5),      # ROI larger than the terrain
     ((421, 380), 140, 25, 3, 6, 7),      # too big for an LDS tile: global reads
+    ((520, 610), 30, 5, 15, 23, 11),     # several chunks and batches per wavefront
 ])
 def test_vix_parity(S, orc, shape, R, ht, hr, K, seed):
     _say("vix", shape, R, ht, hr, K, seed)
