@@ -89,13 +89,16 @@ int siting_device_cus(int32_t *cus_host);
  * linearly interpolated between the two adjacent posts ("Terrain
  * visibility"), and is blocked only if the terrain is strictly above the
  * segment.
- * Draw j of post t = y*ncols+x takes attempts a = 0..63; attempt a uses word
- * a%4 of Philox4x64-10(counter {t, j, a/4, 0}, key {seed, 0}) as u and the
- * candidate  px = bx0 + (((u>>32) * wx) >> 32),
- *            py = by0 + (((u & 0xffffffff) * wy) >> 32)
- * in the terrain-clipped box [bx0, bx0+wx) x [by0, by0+wy) around T; it is
- * accepted iff P != T and |P-T|^2 <= roi^2.  A draw with no accepted attempt
- * counts as not visible.
+ * Post t = y*ncols+x owns one stream of 32-bit words: word a is word a%4 of
+ * Philox4x32-10(counter {t mod 2^32, a/4, t / 2^32, 0},
+ * key {seed mod 2^32, seed / 2^32}).  Proposals take the words in pairs
+ * (u, v):  px = bx0 + (((u >> 8) * wx) >> 24),
+ *          py = by0 + (((v >> 8) * wy) >> 24)
+ * in the terrain-clipped box [bx0, bx0+wx) x [by0, by0+wy) around T; a
+ * proposal is accepted iff P != T and |P-T|^2 <= roi^2.  Draw j is the next
+ * accepted proposal of the stream; after 64 consecutive rejections the draw
+ * fails (counts as not visible) and draw j+1 continues with the next
+ * proposal.
  *   z      : terrain (device), nrows x ncols, leading dimension ld
  *   nrows, ncols >= 2; K in 1..255
  *   count  : out (device), nrows x ncols uint8, contiguous row-major: the

@@ -45,7 +45,7 @@ def _load():
         lib = C.CDLL(_LIB_PATH)
         P = C.c_void_p
         i64, i32, u64 = C.c_int64, C.c_int32, C.c_uint64
-        lib.or_philox4x64_10.argtypes = [P, P, P]
+        lib.or_philox4x32_10.argtypes = [P, P, P]
         lib.or_los.argtypes = [P, i64, i64, i64, i64, i64, i64, i64, i32, i32]
         lib.or_los.restype = C.c_int
         lib.or_vix.argtypes = [P, i64, i64, i64, i32, i32, i32, i32, u64, P, i64, i64]
@@ -93,12 +93,12 @@ def num_threads() -> int:
     return int(_load().or_num_threads())
 
 
-def philox4x64_10(counter, key) -> np.ndarray:
-    """Philox4x64-10 block function (Salmon et al., SC'11)."""
-    c = np.ascontiguousarray(counter, dtype=np.uint64)
-    k = np.ascontiguousarray(key, dtype=np.uint64)
-    out = np.zeros(4, np.uint64)
-    _load().or_philox4x64_10(_ptr(c), _ptr(k), _ptr(out))
+def philox4x32_10(counter, key) -> np.ndarray:
+    """Philox4x32-10 block function (Salmon et al., SC'11)."""
+    c = np.ascontiguousarray(counter, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, np.uint32)
+    _load().or_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
     return out
 
 

@@ -21,7 +21,7 @@
  *    (tangency is visible);
  *  - VIX targets are uniform over the lattice cells of the ROI disk that lie
  *    inside the terrain, drawn by rejection from the terrain-clipped bounding
- *    box with one counter-based Philox4x64-10 stream per post;
+ *    box with one counter-based Philox4x32-10 stream per post;
  *  - FINDMAX blocks are a G_r x G_c grid with floor(i*N/G) boundaries, ranked
  *    by (count desc, elevation desc, linear index asc);
  *  - the viewshed sweeps rays from the observer to every boundary cell of the
@@ -43,33 +43,26 @@ typedef struct {
 } or_observer;
 
 /* ------------------------------------------------------------------------ */
-/* Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11 "Parallel random numbers:
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11 "Parallel random numbers:
  * as easy as 1, 2, 3").  Each round multiplies counter words 0 and 2 by the
- * round multipliers into 128-bit products, and the key is bumped by the
- * Weyl constants between rounds.                                            */
-static void mul128(uint64_t a, uint64_t b, uint64_t *hi, uint64_t *lo)
+ * round multipliers into 64-bit products; the high halves are mixed with the
+ * other two words and the key, the low halves move to words 1 and 3, and the
+ * key is bumped by the Weyl constants between rounds.                       */
+void or_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
 {
-    unsigned __int128 p = (unsigned __int128)a * (unsigned __int128)b;
-    *hi = (uint64_t)(p >> 64);
-    *lo = (uint64_t)p;
-}
-
-void or_philox4x64_10(const uint64_t ctr_in[4], const uint64_t key_in[2], uint64_t out[4])
-{
-    uint64_t x0 = ctr_in[0], x1 = ctr_in[1], x2 = ctr_in[2], x3 = ctr_in[3];
-    uint64_t k0 = key_in[0], k1 = key_in[1];
+    uint32_t x0 = ctr_in[0], x1 = ctr_in[1], x2 = ctr_in[2], x3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
     for (int round = 0; round < 10; round++) {
         if (round > 0) {
-            k0 += 0x9E3779B97F4A7C15ULL;
-            k1 += 0xBB67AE8584CAA73BULL;
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
         }
-        uint64_t hi0, lo0, hi1, lo1;
-        mul128(0xD2E7470EE14C6C93ULL, x0, &hi0, &lo0);
-        mul128(0xCA5A826395121157ULL, x2, &hi1, &lo1);
-        uint64_t n0 = hi1 ^ x1 ^ k0;
-        uint64_t n1 = lo1;
-        uint64_t n2 = hi0 ^ x3 ^ k1;
-        uint64_t n3 = lo0;
+        uint64_t p0 = (uint64_t)0xD2511F53u * x0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * x2;
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+        uint32_t n1 = (uint32_t)p1;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+        uint32_t n3 = (uint32_t)p0;
         x0 = n0; x1 = n1; x2 = n2; x3 = n3;
     }
     out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
@@ -127,23 +120,26 @@ int or_los(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
  * for every post, K receivers drawn uniformly from the ROI disk, each tested
  * for line of sight; the output is the number of visible receivers.
  *
- * Post t (t = y*ncols + x) owns one stream of 64-bit words: word a is word
- * (a mod 4) of Philox4x64-10(counter = {t, a/4, 0, 0}, key = {seed, 0}).  The
- * draws take words in order.  With the terrain-clipped box [bx0,bx1] x
- * [by0,by1] around the post, a word u proposes
- *     px = bx0 + ((u >> 32) * (bx1-bx0+1)) >> 32,
- *     py = by0 + ((u & 0xffffffff) * (by1-by0+1)) >> 32,
- * accepted iff (px,py) != (x,y) and (px-x)^2 + (py-y)^2 <= R^2.  Draw j is
- * the next accepted proposal; after 64 consecutive rejections draw j fails
- * (counts as not visible) and draw j+1 continues with the following word.
- * The K targets of post (x,y) can be dumped with or_vix_targets.           */
+ * Post t (t = y*ncols + x) owns one stream of 32-bit words: word a is word
+ * (a mod 4) of Philox4x32-10(counter = {t mod 2^32, a/4, t / 2^32, 0},
+ * key = {seed mod 2^32, seed / 2^32}).  Proposals take two words (u, v) in
+ * order.  With the terrain-clipped box [bx0,bx1] x [by0,by1] around the
+ * post, (u, v) proposes
+ *     px = bx0 + ((u >> 8) * (bx1-bx0+1)) >> 24,
+ *     py = by0 + ((v >> 8) * (by1-by0+1)) >> 24
+ * (the top 24 bits of each word scaled to the box width, so every column
+ * gets floor or ceil of 2^24/width of the 2^24 values), accepted iff
+ * (px,py) != (x,y) and (px-x)^2 + (py-y)^2 <= R^2.  Draw j is the next
+ * accepted proposal; after 64 consecutive rejections draw j fails (counts as
+ * not visible) and draw j+1 continues with the following proposal.  The K
+ * targets of post (x,y) can be dumped with or_vix_targets.                 */
 #define OR_VIX_MAX_ATTEMPTS 64
 
 typedef struct {
     int64_t t, x, y, bx0, by0;
     uint64_t wx, wy, seed;
-    uint64_t a;          /* next word of the stream */
-    uint64_t blk[4];
+    uint64_t a;          /* next word of the stream (always even) */
+    uint32_t blk[4];
 } vix_stream;
 
 static void vix_stream_init(vix_stream *s, int64_t nrows, int64_t ncols, int64_t x, int64_t y,
@@ -163,16 +159,17 @@ static void vix_stream_init(vix_stream *s, int64_t nrows, int64_t ncols, int64_t
 
 static int vix_draw(vix_stream *s, int32_t R, int64_t *ox, int64_t *oy)
 {
-    uint64_t key[2] = {s->seed, 0};
+    uint32_t key[2] = {(uint32_t)s->seed, (uint32_t)(s->seed >> 32)};
     for (int att = 0; att < OR_VIX_MAX_ATTEMPTS; att++) {
         if ((s->a & 3) == 0) {
-            uint64_t ctr[4] = {(uint64_t)s->t, s->a >> 2, 0, 0};
-            or_philox4x64_10(ctr, key, s->blk);
+            uint32_t ctr[4] = {(uint32_t)s->t, (uint32_t)(s->a >> 2),
+                               (uint32_t)((uint64_t)s->t >> 32), 0};
+            or_philox4x32_10(ctr, key, s->blk);
         }
-        uint64_t u = s->blk[s->a & 3];
-        s->a++;
-        int64_t px = s->bx0 + (int64_t)(((u >> 32) * s->wx) >> 32);
-        int64_t py = s->by0 + (int64_t)(((u & 0xffffffffULL) * s->wy) >> 32);
+        uint64_t u = s->blk[s->a & 3], v = s->blk[(s->a & 3) + 1];
+        s->a += 2;
+        int64_t px = s->bx0 + (int64_t)(((u >> 8) * s->wx) >> 24);
+        int64_t py = s->by0 + (int64_t)(((v >> 8) * s->wy) >> 24);
         int64_t ddx = px - s->x, ddy = py - s->y;
         if ((ddx != 0 || ddy != 0) && ddx * ddx + ddy * ddy <= (int64_t)R * R) {
             *ox = px; *oy = py;

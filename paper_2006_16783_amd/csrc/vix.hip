@@ -24,10 +24,14 @@
 // block of steps whose reads are all issued before any comparison, one LDS
 // round trip per block.
 //
-// Draws: post t owns one Philox4x64-10 stream (word a = word a%4 of the
-// block {t, a/4, 0, 0} under key {seed, 0}); the generator runs only when some
-// lane of the wavefront has used up its block, with all lanes computing it
-// together.
+// Draws: post t owns one Philox4x32-10 stream (word a = word a%4 of the
+// block {t lo, a/4, t hi, 0} under key {seed lo, seed hi}); a proposal takes
+// two words and scales their top 24 bits to the clipped box with the
+// full-rate 24-bit multiplier.  The block index sits in a counter word that
+// the first round does not multiply, so that round's products depend only on
+// the post and are computed once per batch.  The generator runs only when
+// some lane of the wavefront has used up its block, with all lanes computing
+// it together.
 //
 // Exactness: everything is integer.  At major step k of a LOS of length n
 // (k*|minor| = q*n + r) the terrain sample is S = z0*n + (z1-z0)*r and the
@@ -51,35 +55,31 @@ constexpr uint32_t kSkip = 0xFFFFFFFFu;
 // batches in flight.
 constexpr int kVixWaveLds = 2 * 64 * 4;
 
-// Full 128-bit product of two 64-bit words from four 32x32->64 multiply-adds
-// (schoolbook, carries folded into the adds).
-__device__ __forceinline__ void mul128(uint64_t a, uint64_t b, uint64_t &hi, uint64_t &lo)
+// Philox4x32-10 block function (Salmon et al., SC'11): per round two 32x32
+// products (one v_mad_u64_u32 each), their high halves mixed with the other
+// counter words and the key, and the key bumped by the Weyl constants.
+__device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                              uint32_t k0, uint32_t k1, uint32_t out[4])
 {
-    const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
-    const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
-    const uint64_t t = (uint64_t)a0 * b0;
-    const uint64_t u = (uint64_t)a1 * b0 + (t >> 32);
-    const uint64_t v = (uint64_t)a0 * b1 + (uint32_t)u;
-    hi = (uint64_t)a1 * b1 + (u >> 32) + (v >> 32);
-    lo = (v << 32) | (uint32_t)t;
-}
-
-// Philox4x64-10 block function (Salmon et al., SC'11).
-__device__ __forceinline__ void philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
-                                              uint64_t k0, uint64_t k1, uint64_t out[4])
-{
-    constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
-    constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+    constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
 #pragma unroll
     for (int round = 0; round < 10; round++) {
-        uint64_t hi0, lo0, hi1, lo1;
-        mul128(M0, c0, hi0, lo0);
-        mul128(M1, c2, hi1, lo1);
-        uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        const uint64_t p0 = (uint64_t)M0 * c0, p1 = (uint64_t)M1 * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c0 = n0; c1 = (uint32_t)p1; c2 = n2; c3 = (uint32_t)p0;
         k0 += W0; k1 += W1;
     }
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+// High half of a 24x24-bit product (full rate): (a[23:0] * b[23:0]) >> 32.
+__device__ __forceinline__ uint32_t mul_hi_u24(uint32_t a, uint32_t b)
+{
+    uint32_t r;
+    asm("v_mul_hi_u32_u24 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
 }
 
 // 24-bit signed multiply (full rate).  Operands here are a post elevation
@@ -164,8 +164,8 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
     uint64_t t = 0;               // post index = stream counter
     int po = 0, Epost = 0;        // post offset from zb, eye elevation
     int bxo = 0, byo = 0;         // clipped box corner relative to the post
-    uint32_t wx = 0, wy = 0;      // clipped box extent
-    uint64_t blk_next = 0, w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+    uint32_t wx8 = 0, wy8 = 0;    // clipped box extent << 8
+    uint32_t blk_next = 0, w0 = 0, w1 = 0, w2 = 0, w3 = 0;
     int nbuf = 0;
     // the previous batch, whose tests may still run
     bool prev_pending = false, prev_valid = false;
@@ -187,8 +187,8 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
         const int64_t by0 = y - R < 0 ? 0 : y - R, by1 = y + R > nrows - 1 ? nrows - 1 : y + R;
         bxo = (int)(bx0 - x);
         byo = (int)(by0 - y);
-        wx = (uint32_t)(bx1 - bx0 + 1);
-        wy = (uint32_t)(by1 - by0 + 1);
+        wx8 = (uint32_t)(bx1 - bx0 + 1) << 8;
+        wy8 = (uint32_t)(by1 - by0 + 1) << 8;
         blk_next = 0;
         nbuf = 0;
         j0 = 0;
@@ -202,26 +202,27 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
         for (int j = 0; j < kVixChunk; j++)
             e[j] = kSkip;
         int made = 0, att = 0;
+        const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
         while (__any(made < need)) {
             const bool want = made < need && nbuf == 0;
             if (__any(want)) {
-                uint64_t o[4];
-                philox4x64_10(t, blk_next, 0, 0, seed, 0, o);
+                uint32_t o[4];
+                philox4x32_10((uint32_t)t, blk_next, (uint32_t)(t >> 32), 0, k0, k1, o);
                 if (want) {
                     w0 = o[0]; w1 = o[1]; w2 = o[2]; w3 = o[3];
                     blk_next++;
-                    nbuf = 4;
+                    nbuf = 2;
                 }
             }
 #pragma unroll
-            for (int i = 0; i < 4; i++) {
+            for (int i = 0; i < 2; i++) {
                 if (made < need && nbuf > 0) {
-                    const uint64_t u = nbuf == 4 ? w0 : nbuf == 3 ? w1 : nbuf == 2 ? w2 : w3;
+                    const uint32_t u = nbuf == 2 ? w0 : w2, v = nbuf == 2 ? w1 : w3;
                     nbuf--;
                     att++;
-                    // ((u >> 32) * wx) >> 32, i.e. the high word of a 32x32 product
-                    const int dx = bxo + (int)__umulhi((uint32_t)(u >> 32), wx);
-                    const int dy = byo + (int)__umulhi((uint32_t)u, wy);
+                    // top 24 bits of each word scaled to the box: (f * w) >> 24
+                    const int dx = bxo + (int)mul_hi_u24(u >> 8, wx8);
+                    const int dy = byo + (int)mul_hi_u24(v >> 8, wy8);
                     const bool ok = (dx | dy) != 0 && dx * dx + dy * dy <= R2;
                     if (ok || att == kVixMaxAttempts) {
                         // append: shift the lane's queue down one row

@@ -1,5 +1,5 @@
-"""Pins of the CPU oracle against things other than itself: a library
-generator, the paper's printed block counts, closed forms, invariants and a
+"""Pins of the CPU oracle against things other than itself: published
+generator known answers, the paper's printed block counts, closed forms, invariants and a
 pure-Python brute force with exact rational arithmetic (tests/brute.py)."""
 import math
 import os
@@ -18,29 +18,22 @@ def _rand_terrain(rng, nr, nc, lo=0, hi=40):
 
 
 # ---------------------------------------------------------------- RNG ------
-def _dec256(ctr):
-    # counter - 1 over the 256-bit little-endian word vector (wraps at 0)
-    v = sum(int(w) << (64 * i) for i, w in enumerate(ctr))
-    v = (v - 1) % (1 << 256)
-    return [(v >> (64 * i)) & (2**64 - 1) for i in range(4)]
+def _kat_rows():
+    rows = []
+    for line in open(os.path.join(HERE, "golden", "philox4x32_10_kat.txt")):
+        if line.strip() and not line.startswith("#"):
+            w = [int(v, 16) for v in line.split()]
+            assert len(w) == 10
+            rows.append((w[0:4], w[4:6], w[6:10]))
+    return rows
 
 
-@pytest.mark.parametrize("ctr,key", [
-    ([0, 0, 0, 0], [0, 0]),
-    ([1, 2, 3, 4], [5, 6]),
-    ([2**64 - 1] * 4, [2**64 - 1] * 2),
-    ([123456789, 7, 0, 0], [0xdeadbeef, 0]),
-])
-def test_philox_matches_numpy(orc, ctr, key):
-    # numpy's Philox (4x64-10) increments its counter before each block, so a
-    # counter preset to c-1 yields block(c).
-    c = np.array(ctr, dtype=object)
-    prev = _dec256(ctr)
-    bg = np.random.Philox(key=np.array(key, dtype=np.uint64),
-                          counter=np.array(prev, dtype=np.uint64))
-    want = bg.random_raw(4)
-    got = orc.philox4x64_10(np.array([int(v) for v in c], dtype=np.uint64), key)
-    assert [int(v) for v in got] == [int(v) for v in want]
+def test_philox4x32_known_answers(orc):
+    rows = _kat_rows()
+    assert len(rows) == 3
+    for ctr, key, want in rows:
+        got = orc.philox4x32_10(np.array(ctr, np.uint32), np.array(key, np.uint32))
+        assert [int(v) for v in got] == want, (ctr, key)
 
 
 # ---------------------------------------------------------------- LOS ------
@@ -119,32 +112,36 @@ def test_vix_targets_valid_and_counted(orc):
             assert c == cnt[y, x]
 
 
-def test_vix_draw_formula_from_numpy_philox(orc):
-    # post t's words: word a = word (a mod 4) of the Philox block {t, a//4, 0, 0}
-    # keyed {seed, 0}; draws take the accepted proposals in order, a draw
-    # giving up after 64 consecutive rejections.
-    nr, nc, R, seed = 50, 60, 7, 1234
-    for (x, y) in [(0, 0), (30, 20), (59, 49), (3, 45)]:
-        tx, ty = orc.vix_targets(nr, nc, x, y, R, 9, seed)
-        t = y * nc + x
-        bx0, bx1 = max(0, x - R), min(nc - 1, x + R)
-        by0, by1 = max(0, y - R), min(nr - 1, y + R)
-        # numpy's Philox increments its counter before each block
-        words = []
-        for b in range(40):
-            bg = np.random.Philox(key=np.array([seed, 0], np.uint64),
-                                  counter=np.array(_dec256([t, b, 0, 0]), np.uint64))
-            words += [int(w) for w in bg.random_raw(4)]
-        a = 0
-        for j in range(9):
-            while True:
-                u = words[a]
-                a += 1
-                px = bx0 + (((u >> 32) * (bx1 - bx0 + 1)) >> 32)
-                py = by0 + (((u & 0xffffffff) * (by1 - by0 + 1)) >> 32)
-                if (px, py) != (x, y) and (px - x) ** 2 + (py - y) ** 2 <= R * R:
-                    break
-            assert (tx[j], ty[j]) == (px, py)
+def test_vix_draw_stream_layout(orc):
+    # post t's words: word a = word (a mod 4) of the Philox4x32-10 block
+    # {t lo, a//4, t hi, 0} keyed {seed lo, seed hi} (the block function is
+    # pinned by its known answers above); a proposal takes two words and
+    # scales their top 24 bits to the clipped box; draws take the accepted
+    # proposals in order.  A seed above 2^32 and a post index above 2^32 check
+    # the word split of both.
+    cases = [((50, 60), 7, 1234, [(0, 0), (30, 20), (59, 49), (3, 45)]),
+             ((3, 2**31), 1, (7 << 32) | 5, [(2**31 - 1, 2), (2**31 - 3, 1)])]
+    for (nr, nc), R, seed, posts in cases:
+        key = np.array([seed & 0xffffffff, seed >> 32], np.uint32)
+        for (x, y) in posts:
+            tx, ty = orc.vix_targets(nr, nc, x, y, R, 9, seed)
+            t = y * nc + x
+            bx0, bx1 = max(0, x - R), min(nc - 1, x + R)
+            by0, by1 = max(0, y - R), min(nr - 1, y + R)
+            words = []
+            for b in range(60):
+                ctr = np.array([t & 0xffffffff, b, t >> 32, 0], np.uint32)
+                words += [int(w) for w in orc.philox4x32_10(ctr, key)]
+            a = 0
+            for j in range(9):
+                while True:
+                    u, v = words[a], words[a + 1]
+                    a += 2
+                    px = bx0 + (((u >> 8) * (bx1 - bx0 + 1)) >> 24)
+                    py = by0 + (((v >> 8) * (by1 - by0 + 1)) >> 24)
+                    if (px, py) != (x, y) and (px - x) ** 2 + (py - y) ** 2 <= R * R:
+                        break
+                assert (tx[j], ty[j]) == (px, py), (x, y, j)
 
 
 def test_vix_flat_is_full_and_monotone(orc):
