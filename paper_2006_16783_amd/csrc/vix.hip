@@ -2,9 +2,11 @@
 // its ROI disk (stage Vix of the siting process).
 //
 // Layout: the terrain is cut into T x T post tiles; a workgroup stages its
-// tile plus an R-post halo ((T+2R)^2 int16) in LDS when that fits, so every
-// line-of-sight sample is an LDS read; otherwise (large ROI) it reads the
-// terrain through L2 and tiles only give spatial locality.  Tiles are handed
+// tile plus a halo of H = R + s - 1 posts ((T+2H)^2 int16; s LOS steps per
+// block) in LDS when that fits, so every line-of-sight sample is an LDS read
+// and a block's steps past the end of its line (discarded) need no mask;
+// otherwise (large ROI) it reads the terrain through L2, masked, and tiles
+// only give spatial locality.  Tiles are handed
 // to XCDs in contiguous bands so that neighbouring halos share an L2.
 //
 // Scheduling: a line of sight ends at its first blocking sample, so test
@@ -34,9 +36,11 @@
 // it together.
 //
 // Exactness: everything is integer.  At major step k of a LOS of length n
-// (k*|minor| = q*n + r) the terrain sample is S = z0*n + (z1-z0)*r and the
-// segment is E*n + (Z-E)*k; with |z| < 2^15, n <= 4094 and heights <= 2^15
-// every term fits in int32 and the 24-bit multiplier is exact.
+// (k*|minor| = q*n + r) the terrain sample is S = z0*n + (z1-z0)*r, computed
+// as z1*n + (z1-z0)*e with e = r - n in [-n, -1] (e + |minor| >= 0 is then the
+// carry of one add), and the segment is E*n + (Z-E)*k; with |z| < 2^15,
+// n <= 4094 and heights <= 2^15 every term fits in int32 and the 24-bit
+// multipliers are exact.
 #include <cstdlib>
 
 #include "common.hpp"
@@ -51,9 +55,10 @@ constexpr int kVixMaxAttempts = 64;    // consecutive rejections before a draw f
 constexpr int kVixMaxRoi = 4094;       // queue entries hold dx, dy in 13 bits
 constexpr uint32_t kSkip = 0xFFFFFFFFu;
 
-// LDS bytes besides the tile: per wavefront the visible counts of its two
-// batches in flight.
-constexpr int kVixWaveLds = 2 * 64 * 4;
+// Count buffers per wavefront (batches in flight) and the LDS bytes besides
+// the tile: per wavefront kVixBufs x 64 16-bit visible counters.
+constexpr int kVixBufs = 4;
+constexpr int kVixWaveLds = kVixBufs * 64 * 2;
 
 // Philox4x32-10 block function (Salmon et al., SC'11): per round two 32x32
 // products (one v_mad_u64_u32 each), their high halves mixed with the other
@@ -92,6 +97,13 @@ __device__ __forceinline__ int mul_i24(int a, int b)
     return r;
 }
 
+__device__ __forceinline__ int mad_i24(int a, int b, int c)
+{
+    int r;
+    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
 __device__ __forceinline__ uint32_t pack_test(int dx, int dy)
 {
     return ((uint32_t)(dx + 4096) << 13) | (uint32_t)(dy + 4096);
@@ -120,19 +132,23 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
     if (t_id >= tiles_r * tiles_c)
         return;
     const int64_t r0 = (t_id / tiles_c) * T, c0 = (t_id % tiles_c) * T;
-    const int pitch = T + 2 * R;
+    // LDS halo: the ROI plus the steps a block can run past the end of a
+    // line of sight (those reads are discarded, but stay inside the tile)
+    const int H = kLds ? R + kSPI - 1 : R;
+    const int pitch = T + 2 * H;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int16_t *tile = reinterpret_cast<int16_t *>(smem);
-    // visible counts of this wavefront's two batches in flight
-    uint32_t *cnt = reinterpret_cast<uint32_t *>(smem + tile_bytes) + wave * 128;
+    // visible counts of this wavefront's batches in flight: kVixBufs buffers
+    // of 64 16-bit counters, two per 32-bit word
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(smem + tile_bytes) + wave * (kVixBufs * 32);
     if (tid == 0)
         s_batch = 0;
-    cnt[lane] = 0;
-    cnt[64 + lane] = 0;
+    for (int i = lane; i < kVixBufs * 32; i += 64)
+        cnt[i] = 0;
     if (kLds) {
-        const int64_t oy = r0 - R, ox = c0 - R;
-        const int64_t gy0 = oy < 0 ? 0 : oy, gy1 = r0 + T + R > nrows ? nrows : r0 + T + R;
-        const int64_t gx0 = ox < 0 ? 0 : ox, gx1 = c0 + T + R > ncols ? ncols : c0 + T + R;
+        const int64_t oy = r0 - H, ox = c0 - H;
+        const int64_t gy0 = oy < 0 ? 0 : oy, gy1 = r0 + T + H > nrows ? nrows : r0 + T + H;
+        const int64_t gx0 = ox < 0 ? 0 : ox, gx1 = c0 + T + H > ncols ? ncols : c0 + T + H;
         const int w = (int)(gx1 - gx0), h = (int)(gy1 - gy0);
         for (int row = wave; row < h; row += kVixWaves) {
             const int16_t *src = z + (gy0 + row) * ld + gx0;
@@ -142,8 +158,9 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
         }
     }
     __syncthreads();
-    // terrain base: LDS tile origin (r0-R, c0-R), or the global post (r0, c0)
+    // terrain base: LDS tile origin (r0-H, c0-H), or the global post (r0, c0)
     const int16_t *zb = kLds ? tile : z + r0 * ld + c0;
+    const char *tb = reinterpret_cast<const char *>(tile);
     const int rs = kLds ? pitch : (int)ld;
     const int tile_rows = (int)((r0 + T > nrows ? nrows : r0 + T) - r0);
     const int tile_cols = (int)((c0 + T > ncols ? ncols : c0 + T) - c0);
@@ -157,9 +174,16 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
             bt = atomicAdd(&s_batch, 1);
         return __shfl(bt, 0, 64);
     };
+    // this lane's post of batch bt
+    auto post_of = [&](int bt, int &py, int &px) {
+        const int p = bt * 64 + lane;
+        py = p / T;
+        px = p - py * T;
+        return p < nposts && py < tile_rows && px < tile_cols;
+    };
 
     // ---- the batch being queued: this lane's post and its receiver stream
-    int buf = 0;                  // count buffer of the batch being queued
+    int buf = 0, cur_bt = 0;
     bool valid = false;
     uint64_t t = 0;               // post index = stream counter
     int po = 0, Epost = 0;        // post offset from zb, eye elevation
@@ -167,20 +191,20 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
     uint32_t wx8 = 0, wy8 = 0;    // clipped box extent << 8
     uint32_t blk_next = 0, w0 = 0, w1 = 0, w2 = 0, w3 = 0;
     int nbuf = 0;
-    // the previous batch, whose tests may still run
-    bool prev_pending = false, prev_valid = false;
-    uint64_t prev_t = 0;
+    // earlier batches whose tests may still run: bit b of `pending` says
+    // that count buffer b holds batch (bt_of >> 16b) & 0xffff
+    uint32_t pending = 0;
+    uint64_t bt_of = 0;
     // queue of the current chunk: row j of the queue is draw j0+j of every
     // lane's post; e[0] holds row (cursor >> 6) of this lane's post
     uint32_t e[kVixChunk];
     int j0 = 0, kc = 0, cursor = 0, total = 0;
 
     auto setup = [&](int bt) {
-        const int p = bt * 64 + lane;
-        const int py = p / T, px = p - py * T;
-        valid = p < nposts && py < tile_rows && px < tile_cols;
+        int py, px;
+        valid = post_of(bt, py, px);
         const int64_t y = r0 + py, x = c0 + px;
-        po = kLds ? (py + R) * pitch + (px + R) : py * (int)ld + px;
+        po = kLds ? (py + H) * pitch + (px + H) : py * (int)ld + px;
         Epost = valid ? (int)zb[po] + h_t : 0;
         t = (uint64_t)(y * ncols + x);
         const int64_t bx0 = x - R < 0 ? 0 : x - R, bx1 = x + R > ncols - 1 ? ncols - 1 : x + R;
@@ -248,37 +272,53 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
         total = kc * 64;
     };
 
-    auto retire = [&](int bf, bool v, uint64_t tt) {
+    // write out the counts of batch bt (held in buffer bf) and clear them
+    auto retire = [&](int bf, int bt) {
+        int py, px;
+        const bool v = post_of(bt, py, px);
+        uint32_t *w = &cnt[bf * 32 + (lane >> 1)];
+        const uint32_t c = (*w >> ((lane & 1) << 4)) & 0xFFFFu;
         if (v)
-            count[tt] = (uint8_t)cnt[bf * 64 + lane];
-        cnt[bf * 64 + lane] = 0;
+            count[(r0 + py) * ncols + (c0 + px)] = (uint8_t)c;
+        *w = 0;  // both lanes of the word read it above, in wavefront order
+    };
+    auto add_visible = [&](int cidx) {
+        atomicAdd(&cnt[cidx >> 1], 1u << ((cidx & 1) << 4));
     };
 
     {
         const int bt = claim();
         if (bt >= nbatch)
             return;
+        cur_bt = bt;
         setup(bt);
         generate();
     }
     bool more = true;  // further batches may remain in the tile
     bool active = false;
-    int n = 0, mn = 0, r = 0, off = 0, smaj = 0, smin = 0, rhs = 0, dz = 0, k = 0, pl = 0;
+    // LOS state: n major steps, mn minor steps; e = r - n < 0 with r the
+    // minor remainder, kept as an unsigned word so that e + mn >= 0 is the
+    // carry of the add; off: offset of the current post (bytes into the LDS
+    // tile, elements from zb otherwise); rhs: segment height at the current
+    // step (scaled by n); k: steps left; pl: count slot
+    int n = 0, mn = 0, off = 0, smaj = 0, smin = 0, rhs = 0, dz = 0, k = 0, pl = 0;
+    uint32_t eu = 0;
     for (;;) {
         if (cursor >= total) {
-            // queue drained: next chunk of this batch, or the next batch
-            // once no test of the batch before this one is running
+            // queue drained: next chunk of this batch, or the next batch once
+            // the count buffer it takes has no test running
             if (j0 + kc < K) {
                 j0 += kc;
                 generate();
             } else if (more) {
+                const int nb = (buf + 1) & (kVixBufs - 1);
                 bool can = true;
-                if (prev_pending) {
-                    if (__any(active && (pl >> 6) != buf)) {
+                if (pending & (1u << nb)) {
+                    if (__any(active && (pl >> 6) == nb)) {
                         can = false;
                     } else {
-                        retire(buf ^ 1, prev_valid, prev_t);
-                        prev_pending = false;
+                        retire(nb, (int)((bt_of >> (16 * nb)) & 0xFFFF));
+                        pending &= ~(1u << nb);
                     }
                 }
                 if (can) {
@@ -286,10 +326,11 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
                     if (bt >= nbatch) {
                         more = false;
                     } else {
-                        prev_pending = true;
-                        prev_valid = valid;
-                        prev_t = t;
-                        buf ^= 1;
+                        pending |= 1u << buf;
+                        bt_of = (bt_of & ~(0xFFFFull << (16 * buf))) |
+                                ((uint64_t)cur_bt << (16 * buf));
+                        buf = nb;
+                        cur_bt = bt;
                         setup(bt);
                         generate();
                     }
@@ -313,20 +354,22 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
                 const int dy = (int)(ent & 0x1FFF) - 4096;
                 const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
                 const bool xmaj = adx >= ady;
-                const int cidx = buf * 64 + src;
+                const int cidx = (buf << 6) | src;
                 n = xmaj ? adx : ady;
                 if (n <= 1) {
-                    atomicAdd(&cnt[cidx], 1u);  // adjacent: always visible
+                    add_visible(cidx);  // adjacent: always visible
                 } else {
                     const int sx = dx < 0 ? -1 : 1, sy = dy < 0 ? -rs : rs;
+                    const int es = kLds ? 2 : 1;  // offset units per post
                     mn = xmaj ? ady : adx;
-                    smaj = xmaj ? sx : sy;
-                    smin = xmaj ? sy : sx;
-                    off = spo;
-                    const int Zt = (int)zb[spo + (kLds ? mul_i24(dy, rs) : dy * rs) + dx] + h_r;
+                    smaj = (xmaj ? sx : sy) * es;
+                    smin = (xmaj ? sy : sx) * es;
+                    const int tgt = spo + (kLds ? mul_i24(dy, rs) : dy * rs) + dx;
+                    const int Zt = (int)zb[tgt] + h_r;
+                    off = spo * es;
                     rhs = sE * n;
                     dz = Zt - sE;
-                    r = 0;
+                    eu = (uint32_t)-n;
                     k = n - 1;  // steps left
                     pl = cidx;
                     active = true;
@@ -341,52 +384,55 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
             cursor = c1;
         }
         if (active) {
-            // kSPI steps at once: addresses first, then every read (masked
-            // past the end of the LOS), then the comparisons, so the step
-            // loop waits for LDS once per block of steps
-            int so[kSPI], sr[kSPI], sa[kSPI], sb[kSPI];
+            // kSPI steps at once: positions and reads first, then the
+            // comparisons, so the step loop waits for memory once per block
+            int sa[kSPI], sb[kSPI], se[kSPI];
 #pragma unroll
             for (int sp = 0; sp < kSPI; sp++) {
-                r += mn;
-                off += smaj;
-                if (r >= n) {
-                    r -= n;
-                    off += smin;
+                uint32_t e1;
+                const bool wrap = __builtin_add_overflow(eu, (uint32_t)mn, &e1);
+                eu = wrap ? e1 - (uint32_t)n : e1;
+                off += smaj + (wrap ? smin : 0);
+                se[sp] = (int)eu;
+                if (kLds) {
+                    // past the end of the LOS these reads land in the halo
+                    sa[sp] = *reinterpret_cast<const int16_t *>(tb + off);
+                    sb[sp] = *reinterpret_cast<const int16_t *>(tb + off + smin);
+                } else {
+                    sa[sp] = 0;
+                    sb[sp] = 0;
+                    if (sp < k) {
+                        sa[sp] = zb[off];
+                        sb[sp] = zb[off + smin];  // in the observer-target box
+                    }
                 }
-                so[sp] = off;
-                sr[sp] = r;
             }
-#pragma unroll
-            for (int sp = 0; sp < kSPI; sp++) {
-                sa[sp] = 0;
-                sb[sp] = 0;
-                if (sp < k) {
-                    sa[sp] = zb[so[sp]];
-                    sb[sp] = zb[so[sp] + smin];  // in the observer-target box
-                }
-            }
-            int first = kSPI;  // first blocking step of the block
+            // terrain above the segment: z0*n + (z1-z0)*r = z1*n + (z1-z0)*e
+            bool blocked = false;
+            int first = kSPI;
 #pragma unroll
             for (int sp = 0; sp < kSPI; sp++) {
                 rhs += dz;
-                const int S = mul_i24(sa[sp], n) + mul_i24(sb[sp] - sa[sp], sr[sp]);
-                if (sp < k && S > rhs && first == kSPI)
+                const int S = mad_i24(sb[sp] - sa[sp], se[sp], mul_i24(sb[sp], n));
+                const bool bs = sp < k && S > rhs;
+                blocked |= bs;
+                if (kCount && bs && first == kSPI)
                     first = sp;
             }
-            const bool blocked = first < kSPI;
             if (kCount)
                 steps += blocked ? first + 1 : (k < kSPI ? k : kSPI);
             k -= kSPI;
             if (blocked || k <= 0) {
                 if (!blocked)
-                    atomicAdd(&cnt[pl], 1u);
+                    add_visible(pl);
                 active = false;
             }
         }
     }
-    retire(buf, valid, t);
-    if (prev_pending)
-        retire(buf ^ 1, prev_valid, prev_t);
+    retire(buf, cur_bt);
+    for (int bf = 0; bf < kVixBufs; bf++)
+        if (pending & (1u << bf))
+            retire(bf, (int)((bt_of >> (16 * bf)) & 0xFFFF));
     if (kCount) {
         atomicAdd(&stats[0], (unsigned long long)steps);
         atomicAdd(&stats[1], (unsigned long long)tests);
@@ -424,14 +470,20 @@ static int vix_launch(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld
         set_error("%s: roi %d above the supported %d", fn, roi, kVixMaxRoi);
         return SITING_E_UNSUPPORTED;
     }
-    // Largest tile side (multiple of 8, <= 128) whose haloed tile and the
-    // wavefront queues fit in LDS.
-    // (every instantiation declares the same static LDS)
+    static const int spi = [] {
+        const char *e = getenv("SITING_VIX_STEPS_PER_ITER");
+        int v = e ? atoi(e) : 8;
+        return v == 2 ? 2 : v == 4 ? 4 : 8;
+    }();
+    // Largest tile side (multiple of 8, <= 128) whose haloed tile (halo: the
+    // ROI plus spi-1 steps past a line's end) and the count buffers fit in
+    // LDS (every instantiation declares the same static LDS).
     const int lds_max = kernel_max_dynamic_lds(reinterpret_cast<const void *>(&vix_kernel<true, false, 8>));
     const int queue_bytes = kVixWaves * kVixWaveLds;
+    const int halo = roi + spi - 1;
     int T = 0;
     for (int c = 128; c >= 16; c -= 8) {
-        int64_t bytes = (((int64_t)(c + 2 * roi) * (c + 2 * roi) * 2 + 15) & ~15ll) + queue_bytes;
+        int64_t bytes = (((int64_t)(c + 2 * halo) * (c + 2 * halo) * 2 + 15) & ~15ll) + queue_bytes;
         if (bytes <= lds_max) {
             T = c;
             break;
@@ -452,7 +504,7 @@ static int vix_launch(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld
         set_error("%s: terrain too large", fn);
         return SITING_E_UNSUPPORTED;
     }
-    const int tile_bytes = use_lds ? (int)((((int64_t)(T + 2 * roi) * (T + 2 * roi) * 2) + 15) & ~15ll) : 0;
+    const int tile_bytes = use_lds ? (int)((((int64_t)(T + 2 * halo) * (T + 2 * halo) * 2) + 15) & ~15ll) : 0;
     const size_t lds = (size_t)tile_bytes + queue_bytes;
     hipStream_t s = as_stream(stream);
     if (stats) {
@@ -461,11 +513,6 @@ static int vix_launch(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld
         if (rc != SITING_OK)
             return rc;
     }
-    static const int spi = [] {
-        const char *e = getenv("SITING_VIX_STEPS_PER_ITER");
-        int v = e ? atoi(e) : 8;
-        return v == 2 ? 2 : v == 4 ? 4 : 8;
-    }();
 #define VIX_LAUNCH(LDS, CNT, SPI)                                                              \
     hipLaunchKernelGGL((vix_kernel<LDS, CNT, SPI>), dim3((unsigned)grid), dim3(kVixThreads),   \
                        lds, s, z, nrows, ncols, ld, roi, h_t, h_r, K, seed, count, T, tiles_r,  \
