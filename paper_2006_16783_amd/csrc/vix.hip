@@ -109,6 +109,14 @@ __device__ __forceinline__ uint32_t pack_test(int dx, int dy)
     return ((uint32_t)(dx + 4096) << 13) | (uint32_t)(dy + 4096);
 }
 
+// LDS read at a byte address (the address includes the tile's base, so the
+// load needs no add).
+typedef const int16_t __attribute__((address_space(3))) lds_i16;
+__device__ __forceinline__ int lds_read_i16(int addr)
+{
+    return *reinterpret_cast<lds_i16 *>((uintptr_t)(uint32_t)addr);
+}
+
 __device__ __forceinline__ uint32_t lane_read(int src, uint32_t v)
 {
     return (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)v);
@@ -160,7 +168,8 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
     __syncthreads();
     // terrain base: LDS tile origin (r0-H, c0-H), or the global post (r0, c0)
     const int16_t *zb = kLds ? tile : z + r0 * ld + c0;
-    const char *tb = reinterpret_cast<const char *>(tile);
+    // LDS byte address of the tile
+    const int tb = (int)(uint32_t)(uintptr_t)(const __attribute__((address_space(3))) char *)tile;
     const int rs = kLds ? pitch : (int)ld;
     const int tile_rows = (int)((r0 + T > nrows ? nrows : r0 + T) - r0);
     const int tile_cols = (int)((c0 + T > ncols ? ncols : c0 + T) - c0);
@@ -298,8 +307,8 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
     bool active = false;
     // LOS state: n major steps, mn minor steps; e = r - n < 0 with r the
     // minor remainder, kept as an unsigned word so that e + mn >= 0 is the
-    // carry of the add; off: offset of the current post (bytes into the LDS
-    // tile, elements from zb otherwise); rhs: segment height at the current
+    // carry of the add; off: the current post (its LDS byte address, or its
+    // offset in elements from zb); rhs: segment height at the current
     // step (scaled by n); k: steps left; pl: count slot
     int n = 0, mn = 0, off = 0, smaj = 0, smin = 0, rhs = 0, dz = 0, k = 0, pl = 0;
     uint32_t eu = 0;
@@ -366,7 +375,7 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
                     smin = (xmaj ? sy : sx) * es;
                     const int tgt = spo + (kLds ? mul_i24(dy, rs) : dy * rs) + dx;
                     const int Zt = (int)zb[tgt] + h_r;
-                    off = spo * es;
+                    off = kLds ? tb + spo * 2 : spo;
                     rhs = sE * n;
                     dz = Zt - sE;
                     eu = (uint32_t)-n;
@@ -396,8 +405,8 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
                 se[sp] = (int)eu;
                 if (kLds) {
                     // past the end of the LOS these reads land in the halo
-                    sa[sp] = *reinterpret_cast<const int16_t *>(tb + off);
-                    sb[sp] = *reinterpret_cast<const int16_t *>(tb + off + smin);
+                    sa[sp] = lds_read_i16(off);
+                    sb[sp] = lds_read_i16(off + smin);
                 } else {
                     sa[sp] = 0;
                     sb[sp] = 0;
