@@ -91,14 +91,15 @@ int siting_device_cus(int32_t *cus_host);
  * segment.
  * Post t = y*ncols+x owns one stream of 32-bit words: word a is word a%4 of
  * Philox4x32-10(counter {t mod 2^32, a/4, t / 2^32, 0},
- * key {seed mod 2^32, seed / 2^32}).  Proposals take the words in pairs
- * (u, v):  px = bx0 + (((u >> 8) * wx) >> 24),
- *          py = by0 + (((v >> 8) * wy) >> 24)
- * in the terrain-clipped box [bx0, bx0+wx) x [by0, by0+wy) around T; a
- * proposal is accepted iff P != T and |P-T|^2 <= roi^2.  Draw j is the next
- * accepted proposal of the stream; after 64 consecutive rejections the draw
- * fails (counts as not visible) and draw j+1 continues with the next
- * proposal.
+ * key {seed mod 2^32, seed / 2^32}).  Each word u proposes one receiver in
+ * the terrain-clipped box [bx0, bx0+wx) x [by0, by0+wy) around T: with
+ * mx = (u & 0xffff) * wx and my = (u >> 16) * wy (Lemire's multiply-shift),
+ * the proposal is rejected if (mx & 0xffff) < 2^16 mod wx or
+ * (my & 0xffff) < 2^16 mod wy, else P = (bx0 + (mx >> 16), by0 + (my >> 16))
+ * (exactly uniform over the box); it is accepted iff also P != T and
+ * |P-T|^2 <= roi^2.  Draw j is the next accepted proposal of the stream;
+ * after 64 consecutive rejections the draw fails (counts as not visible)
+ * and draw j+1 continues with the next word.
  *   z      : terrain (device), nrows x ncols, leading dimension ld
  *   nrows, ncols >= 2; K in 1..255
  *   count  : out (device), nrows x ncols uint8, contiguous row-major: the

@@ -122,23 +122,25 @@ int or_los(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
  *
  * Post t (t = y*ncols + x) owns one stream of 32-bit words: word a is word
  * (a mod 4) of Philox4x32-10(counter = {t mod 2^32, a/4, t / 2^32, 0},
- * key = {seed mod 2^32, seed / 2^32}).  Proposals take two words (u, v) in
- * order.  With the terrain-clipped box [bx0,bx1] x [by0,by1] around the
- * post, (u, v) proposes
- *     px = bx0 + ((u >> 8) * (bx1-bx0+1)) >> 24,
- *     py = by0 + ((v >> 8) * (by1-by0+1)) >> 24
- * (the top 24 bits of each word scaled to the box width, so every column
- * gets floor or ceil of 2^24/width of the 2^24 values), accepted iff
- * (px,py) != (x,y) and (px-x)^2 + (py-y)^2 <= R^2.  Draw j is the next
- * accepted proposal; after 64 consecutive rejections draw j fails (counts as
- * not visible) and draw j+1 continues with the following proposal.  The K
- * targets of post (x,y) can be dumped with or_vix_targets.                 */
+ * key = {seed mod 2^32, seed / 2^32}).  Each word u makes one proposal in
+ * the terrain-clipped box [bx0, bx0+wx) x [by0, by0+wy) around the post: its
+ * low and high 16 bits fx, fy are scaled to the box widths by Lemire's
+ * multiply-shift with rejection (Lemire, "Fast random integer generation in
+ * an interval", ACM TOMACS 2019):
+ *     mx = fx * wx,  accepted only if (mx mod 2^16) >= 2^16 mod wx,
+ *     px = bx0 + mx / 2^16,
+ * and the same for y, which makes (px, py) exactly uniform over the box.
+ * The proposal is accepted iff both scalings accept, (px,py) != (x,y) and
+ * (px-x)^2 + (py-y)^2 <= R^2.  Draw j is the next accepted proposal; after 64
+ * consecutive rejections draw j fails (counts as not visible) and draw j+1
+ * continues with the following word.  The K targets of post (x,y) can be
+ * dumped with or_vix_targets.                                              */
 #define OR_VIX_MAX_ATTEMPTS 64
 
 typedef struct {
     int64_t t, x, y, bx0, by0;
     uint64_t wx, wy, seed;
-    uint64_t a;          /* next word of the stream (always even) */
+    uint64_t a;          /* next word of the stream */
     uint32_t blk[4];
 } vix_stream;
 
@@ -157,6 +159,17 @@ static void vix_stream_init(vix_stream *s, int64_t nrows, int64_t ncols, int64_t
     s->a = 0;
 }
 
+/* Lemire's bounded integer from a 16-bit field f: 1 and *v in [0, w), or 0
+ * when the field falls in the rejected sliver. */
+static int lemire16(uint64_t f, uint64_t w, int64_t *v)
+{
+    uint64_t m = f * w;
+    if ((m & 0xffff) < (65536 % w))
+        return 0;
+    *v = (int64_t)(m >> 16);
+    return 1;
+}
+
 static int vix_draw(vix_stream *s, int32_t R, int64_t *ox, int64_t *oy)
 {
     uint32_t key[2] = {(uint32_t)s->seed, (uint32_t)(s->seed >> 32)};
@@ -166,10 +179,12 @@ static int vix_draw(vix_stream *s, int32_t R, int64_t *ox, int64_t *oy)
                                (uint32_t)((uint64_t)s->t >> 32), 0};
             or_philox4x32_10(ctr, key, s->blk);
         }
-        uint64_t u = s->blk[s->a & 3], v = s->blk[(s->a & 3) + 1];
-        s->a += 2;
-        int64_t px = s->bx0 + (int64_t)(((u >> 8) * s->wx) >> 24);
-        int64_t py = s->by0 + (int64_t)(((v >> 8) * s->wy) >> 24);
+        uint64_t u = s->blk[s->a & 3];
+        s->a++;
+        int64_t ox_, oy_;
+        if (!lemire16(u & 0xffff, s->wx, &ox_) || !lemire16(u >> 16, s->wy, &oy_))
+            continue;
+        int64_t px = s->bx0 + ox_, py = s->by0 + oy_;
         int64_t ddx = px - s->x, ddy = py - s->y;
         if ((ddx != 0 || ddy != 0) && ddx * ddx + ddy * ddy <= (int64_t)R * R) {
             *ox = px; *oy = py;

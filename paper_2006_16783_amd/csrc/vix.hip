@@ -27,13 +27,13 @@
 // round trip per block.
 //
 // Draws: post t owns one Philox4x32-10 stream (word a = word a%4 of the
-// block {t lo, a/4, t hi, 0} under key {seed lo, seed hi}); a proposal takes
-// two words and scales their top 24 bits to the clipped box with the
-// full-rate 24-bit multiplier.  The block index sits in a counter word that
-// the first round does not multiply, so that round's products depend only on
-// the post and are computed once per batch.  The generator runs only when
-// some lane of the wavefront has used up its block, with all lanes computing
-// it together.
+// block {t lo, a/4, t hi, 0} under key {seed lo, seed hi}); each word
+// proposes one receiver, its 16-bit halves scaled to the clipped box by
+// Lemire's multiply-shift with rejection (exactly uniform; full-rate 24-bit
+// multiplies).  The block index sits in a counter word that the first round
+// does not multiply, so that round's products depend only on the post and
+// are computed once per batch.  The generator runs only when some lane of
+// the wavefront has used up its block, with all lanes computing it together.
 //
 // Exactness: everything is integer.  At major step k of a LOS of length n
 // (k*|minor| = q*n + r) the terrain sample is S = z0*n + (z1-z0)*r, computed
@@ -56,9 +56,9 @@ constexpr int kVixMaxRoi = 4094;       // queue entries hold dx, dy in 13 bits
 constexpr uint32_t kSkip = 0xFFFFFFFFu;
 
 // Count buffers per wavefront (batches in flight) and the LDS bytes besides
-// the tile: per wavefront kVixBufs x 64 16-bit visible counters.
+// the tile: per wavefront kVixBufs x 64 8-bit visible counters (K <= 255).
 constexpr int kVixBufs = 4;
-constexpr int kVixWaveLds = kVixBufs * 64 * 2;
+constexpr int kVixWaveLds = kVixBufs * 64;
 
 // Philox4x32-10 block function (Salmon et al., SC'11): per round two 32x32
 // products (one v_mad_u64_u32 each), their high halves mixed with the other
@@ -77,14 +77,6 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
         k0 += W0; k1 += W1;
     }
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
-}
-
-// High half of a 24x24-bit product (full rate): (a[23:0] * b[23:0]) >> 32.
-__device__ __forceinline__ uint32_t mul_hi_u24(uint32_t a, uint32_t b)
-{
-    uint32_t r;
-    asm("v_mul_hi_u32_u24 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-    return r;
 }
 
 // 24-bit signed multiply (full rate).  Operands here are a post elevation
@@ -128,7 +120,8 @@ template <bool kLds, bool kCount, int kSPI>
 __global__ __launch_bounds__(kVixThreads) void vix_kernel(
     const int16_t *__restrict__ z, int64_t nrows, int64_t ncols, int64_t ld, int R, int h_t,
     int h_r, int K, uint64_t seed, uint8_t *__restrict__ count, int T, int64_t tiles_r,
-    int64_t tiles_c, int64_t per_xcd, int tile_bytes, unsigned long long *__restrict__ stats)
+    int64_t tiles_c, int64_t per_xcd, int tile_bytes, int dma,
+    unsigned long long *__restrict__ stats)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_batch;
@@ -143,30 +136,57 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
     // LDS halo: the ROI plus the steps a block can run past the end of a
     // line of sight (those reads are discarded, but stay inside the tile)
     const int H = kLds ? R + kSPI - 1 : R;
-    const int pitch = T + 2 * H;
+    // LDS rows hold T+2H posts starting at an even terrain column (so that
+    // post pairs are dwords on both sides), padded to an even pitch
+    const int pitch = T + 2 * H + 2;
+    const int64_t ox = c0 - H, oxl = ox - (ox & 1), oy = r0 - H;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int16_t *tile = reinterpret_cast<int16_t *>(smem);
     // visible counts of this wavefront's batches in flight: kVixBufs buffers
-    // of 64 16-bit counters, two per 32-bit word
-    uint32_t *cnt = reinterpret_cast<uint32_t *>(smem + tile_bytes) + wave * (kVixBufs * 32);
+    // of 64 8-bit counters, four per 32-bit word
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(smem + tile_bytes) + wave * (kVixBufs * 16);
     if (tid == 0)
         s_batch = 0;
-    for (int i = lane; i < kVixBufs * 32; i += 64)
-        cnt[i] = 0;
+    if (lane < kVixBufs * 16)
+        cnt[lane] = 0;
     if (kLds) {
-        const int64_t oy = r0 - H, ox = c0 - H;
-        const int64_t gy0 = oy < 0 ? 0 : oy, gy1 = r0 + T + H > nrows ? nrows : r0 + T + H;
-        const int64_t gx0 = ox < 0 ? 0 : ox, gx1 = c0 + T + H > ncols ? ncols : c0 + T + H;
-        const int w = (int)(gx1 - gx0), h = (int)(gy1 - gy0);
-        for (int row = wave; row < h; row += kVixWaves) {
-            const int16_t *src = z + (gy0 + row) * ld + gx0;
-            int16_t *dst = tile + (gy0 + row - oy) * pitch + (gx0 - ox);
-            for (int col = lane; col < w; col += 64)
-                dst[col] = src[col];
+        const int rows = T + 2 * H;
+        const int64_t gy0 = oy < 0 ? 0 : oy, gy1 = oy + rows > nrows ? nrows : oy + rows;
+        if (dma) {
+            // each wavefront streams its rows straight into LDS (global_load_lds:
+            // lane i of a load writes the dword at the wavefront's LDS base + 4i),
+            // every load of the tile in flight before the one wait below
+            const bool interior = oy >= 0 && oy + rows <= nrows && oxl >= 0 && oxl + pitch <= ncols;
+            const int dw_row = pitch >> 1;
+            uint32_t *tdw = reinterpret_cast<uint32_t *>(tile);
+            for (int lr = wave; lr < rows; lr += kVixWaves) {
+                const int64_t gy = oy + lr;
+                if (gy < gy0 || gy >= gy1)
+                    continue;
+                const int16_t *srow = z + gy * ld;
+                for (int k0 = 0; k0 < dw_row; k0 += 64) {
+                    const int k = k0 + lane;
+                    const int64_t c = oxl + 2 * k;
+                    if (k < dw_row && (interior || (c >= 0 && c < ncols)))
+                        __builtin_amdgcn_global_load_lds(
+                            reinterpret_cast<const uint32_t *>(srow + c), tdw + lr * dw_row + k0, 4,
+                            0, 0);
+                }
+            }
+            __builtin_amdgcn_s_waitcnt(0);
+        } else {
+            const int64_t gx0 = ox < 0 ? 0 : ox, gx1 = c0 + T + H > ncols ? ncols : c0 + T + H;
+            const int w = (int)(gx1 - gx0), h = (int)(gy1 - gy0);
+            for (int row = wave; row < h; row += kVixWaves) {
+                const int16_t *src = z + (gy0 + row) * ld + gx0;
+                int16_t *dst = tile + (gy0 + row - oy) * pitch + (gx0 - oxl);
+                for (int col = lane; col < w; col += 64)
+                    dst[col] = src[col];
+            }
         }
     }
     __syncthreads();
-    // terrain base: LDS tile origin (r0-H, c0-H), or the global post (r0, c0)
+    // terrain base: LDS tile origin (r0-H, oxl), or the global post (r0, c0)
     const int16_t *zb = kLds ? tile : z + r0 * ld + c0;
     // LDS byte address of the tile
     const int tb = (int)(uint32_t)(uintptr_t)(const __attribute__((address_space(3))) char *)tile;
@@ -197,7 +217,8 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
     uint64_t t = 0;               // post index = stream counter
     int po = 0, Epost = 0;        // post offset from zb, eye elevation
     int bxo = 0, byo = 0;         // clipped box corner relative to the post
-    uint32_t wx8 = 0, wy8 = 0;    // clipped box extent << 8
+    uint32_t wx = 0, wy = 0;      // clipped box extent
+    uint32_t tx = 0, ty = 0;      // Lemire thresholds 2^16 mod wx, wy
     uint32_t blk_next = 0, w0 = 0, w1 = 0, w2 = 0, w3 = 0;
     int nbuf = 0;
     // earlier batches whose tests may still run: bit b of `pending` says
@@ -213,15 +234,17 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
         int py, px;
         valid = post_of(bt, py, px);
         const int64_t y = r0 + py, x = c0 + px;
-        po = kLds ? (py + H) * pitch + (px + H) : py * (int)ld + px;
+        po = kLds ? (py + H) * pitch + (px + (int)(c0 - oxl)) : py * (int)ld + px;
         Epost = valid ? (int)zb[po] + h_t : 0;
         t = (uint64_t)(y * ncols + x);
         const int64_t bx0 = x - R < 0 ? 0 : x - R, bx1 = x + R > ncols - 1 ? ncols - 1 : x + R;
         const int64_t by0 = y - R < 0 ? 0 : y - R, by1 = y + R > nrows - 1 ? nrows - 1 : y + R;
         bxo = (int)(bx0 - x);
         byo = (int)(by0 - y);
-        wx8 = (uint32_t)(bx1 - bx0 + 1) << 8;
-        wy8 = (uint32_t)(by1 - by0 + 1) << 8;
+        wx = (uint32_t)(bx1 - bx0 + 1);
+        wy = (uint32_t)(by1 - by0 + 1);
+        tx = 65536u % wx;
+        ty = 65536u % wy;
         blk_next = 0;
         nbuf = 0;
         j0 = 0;
@@ -244,19 +267,21 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
                 if (want) {
                     w0 = o[0]; w1 = o[1]; w2 = o[2]; w3 = o[3];
                     blk_next++;
-                    nbuf = 2;
+                    nbuf = 4;
                 }
             }
 #pragma unroll
-            for (int i = 0; i < 2; i++) {
+            for (int i = 0; i < 4; i++) {
                 if (made < need && nbuf > 0) {
-                    const uint32_t u = nbuf == 2 ? w0 : w2, v = nbuf == 2 ? w1 : w3;
+                    const uint32_t u = nbuf == 4 ? w0 : nbuf == 3 ? w1 : nbuf == 2 ? w2 : w3;
                     nbuf--;
                     att++;
-                    // top 24 bits of each word scaled to the box: (f * w) >> 24
-                    const int dx = bxo + (int)mul_hi_u24(u >> 8, wx8);
-                    const int dy = byo + (int)mul_hi_u24(v >> 8, wy8);
-                    const bool ok = (dx | dy) != 0 && dx * dx + dy * dy <= R2;
+                    // 16-bit halves scaled to the box, Lemire's rejection
+                    const uint32_t mx = __umul24(u & 0xFFFFu, wx), my = __umul24(u >> 16, wy);
+                    const int dx = bxo + (int)(mx >> 16);
+                    const int dy = byo + (int)(my >> 16);
+                    const bool ok = (mx & 0xFFFFu) >= tx && (my & 0xFFFFu) >= ty &&
+                                    (dx | dy) != 0 && __mul24(dx, dx) + __mul24(dy, dy) <= R2;
                     if (ok || att == kVixMaxAttempts) {
                         // append: shift the lane's queue down one row
 #pragma unroll
@@ -285,14 +310,14 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
     auto retire = [&](int bf, int bt) {
         int py, px;
         const bool v = post_of(bt, py, px);
-        uint32_t *w = &cnt[bf * 32 + (lane >> 1)];
-        const uint32_t c = (*w >> ((lane & 1) << 4)) & 0xFFFFu;
+        uint32_t *w = &cnt[bf * 16 + (lane >> 2)];
+        const uint32_t c = (*w >> ((lane & 3) << 3)) & 0xFFu;
         if (v)
             count[(r0 + py) * ncols + (c0 + px)] = (uint8_t)c;
-        *w = 0;  // both lanes of the word read it above, in wavefront order
+        *w = 0;  // the four lanes of the word read it above, in wavefront order
     };
     auto add_visible = [&](int cidx) {
-        atomicAdd(&cnt[cidx >> 1], 1u << ((cidx & 1) << 4));
+        atomicAdd(&cnt[cidx >> 2], 1u << ((cidx & 3) << 3));
     };
 
     {
@@ -492,7 +517,7 @@ static int vix_launch(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld
     const int halo = roi + spi - 1;
     int T = 0;
     for (int c = 128; c >= 16; c -= 8) {
-        int64_t bytes = (((int64_t)(c + 2 * halo) * (c + 2 * halo) * 2 + 15) & ~15ll) + queue_bytes;
+        int64_t bytes = (((int64_t)(c + 2 * halo) * (c + 2 * halo + 2) * 2 + 15) & ~15ll) + queue_bytes;
         if (bytes <= lds_max) {
             T = c;
             break;
@@ -513,7 +538,9 @@ static int vix_launch(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld
         set_error("%s: terrain too large", fn);
         return SITING_E_UNSUPPORTED;
     }
-    const int tile_bytes = use_lds ? (int)((((int64_t)(T + 2 * halo) * (T + 2 * halo) * 2) + 15) & ~15ll) : 0;
+    const int tile_bytes = use_lds ? (int)((((int64_t)(T + 2 * halo) * (T + 2 * halo + 2) * 2) + 15) & ~15ll) : 0;
+    // direct terrain-to-LDS loads need dword-aligned post pairs in every row
+    const int dma = (ld % 2 == 0) && ((uintptr_t)z % 4 == 0);
     const size_t lds = (size_t)tile_bytes + queue_bytes;
     hipStream_t s = as_stream(stream);
     if (stats) {
@@ -525,7 +552,7 @@ static int vix_launch(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld
 #define VIX_LAUNCH(LDS, CNT, SPI)                                                              \
     hipLaunchKernelGGL((vix_kernel<LDS, CNT, SPI>), dim3((unsigned)grid), dim3(kVixThreads),   \
                        lds, s, z, nrows, ncols, ld, roi, h_t, h_r, K, seed, count, T, tiles_r,  \
-                       tiles_c, per_xcd, tile_bytes, stats)
+                       tiles_c, per_xcd, tile_bytes, dma, stats)
 #define VIX_SPI(LDS, CNT)                    \
     do {                                     \
         if (spi == 2)                        \

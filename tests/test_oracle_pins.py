@@ -115,12 +115,13 @@ def test_vix_targets_valid_and_counted(orc):
 def test_vix_draw_stream_layout(orc):
     # post t's words: word a = word (a mod 4) of the Philox4x32-10 block
     # {t lo, a//4, t hi, 0} keyed {seed lo, seed hi} (the block function is
-    # pinned by its known answers above); a proposal takes two words and
-    # scales their top 24 bits to the clipped box; draws take the accepted
-    # proposals in order.  A seed above 2^32 and a post index above 2^32 check
-    # the word split of both.
+    # pinned by its known answers above); each word proposes one receiver, its
+    # two 16-bit halves scaled to the clipped box by Lemire's multiply-shift
+    # with rejection; draws take the accepted proposals in order.  A seed above
+    # 2^32 and a post index above 2^32 check the word split of both.
     cases = [((50, 60), 7, 1234, [(0, 0), (30, 20), (59, 49), (3, 45)]),
-             ((3, 2**31), 1, (7 << 32) | 5, [(2**31 - 1, 2), (2**31 - 3, 1)])]
+             ((3, 2**31), 1, (7 << 32) | 5, [(2**31 - 1, 2), (2**31 - 3, 1)]),
+             ((900, 900), 300, 77, [(450, 450), (0, 899)])]
     for (nr, nc), R, seed, posts in cases:
         key = np.array([seed & 0xffffffff, seed >> 32], np.uint32)
         for (x, y) in posts:
@@ -128,6 +129,7 @@ def test_vix_draw_stream_layout(orc):
             t = y * nc + x
             bx0, bx1 = max(0, x - R), min(nc - 1, x + R)
             by0, by1 = max(0, y - R), min(nr - 1, y + R)
+            wx, wy = bx1 - bx0 + 1, by1 - by0 + 1
             words = []
             for b in range(60):
                 ctr = np.array([t & 0xffffffff, b, t >> 32, 0], np.uint32)
@@ -135,13 +137,29 @@ def test_vix_draw_stream_layout(orc):
             a = 0
             for j in range(9):
                 while True:
-                    u, v = words[a], words[a + 1]
-                    a += 2
-                    px = bx0 + (((u >> 8) * (bx1 - bx0 + 1)) >> 24)
-                    py = by0 + (((v >> 8) * (by1 - by0 + 1)) >> 24)
+                    u = words[a]
+                    a += 1
+                    mx, my = (u & 0xffff) * wx, (u >> 16) * wy
+                    if (mx & 0xffff) < 65536 % wx or (my & 0xffff) < 65536 % wy:
+                        continue
+                    px, py = bx0 + (mx >> 16), by0 + (my >> 16)
                     if (px, py) != (x, y) and (px - x) ** 2 + (py - y) ** 2 <= R * R:
                         break
                 assert (tx[j], ty[j]) == (px, py), (x, y, j)
+
+
+def test_lemire_scaling_is_exactly_uniform():
+    # the box scaling of one coordinate: every 16-bit field value either
+    # rejected or mapped, each of the w outputs hit by exactly floor(2^16/w)
+    # values (the property that makes the draw exactly uniform)
+    for w in (1, 3, 201, 255, 256, 257, 1000, 8189):
+        t = 65536 % w
+        hits = np.zeros(w, np.int64)
+        for f in range(65536):
+            m = f * w
+            if (m & 0xffff) >= t:
+                hits[m >> 16] += 1
+        assert (hits == 65536 // w).all(), w
 
 
 def test_vix_flat_is_full_and_monotone(orc):
