@@ -12,7 +12,8 @@
 // keeping a sorted register top-k; a threshold test makes insertions rare.
 // The per-lane lists are then merged by k rounds of a workgroup argmax in
 // which the winning lane pops its list head.
-// HBM-bound: 3 bytes per post (u8 key + int16 z), read once, coalesced.
+// HBM-bound: 3 bytes per post (u8 key + int16 z), read once, coalesced; with
+// 16-byte aligned rows each lane streams 16 posts per step in 16-byte loads.
 #include "common.hpp"
 
 namespace siting {
@@ -57,7 +58,9 @@ __device__ __forceinline__ void topk_insert(uint64_t (&top)[KMAX], uint64_t key)
     }
 }
 
-template <int KMAX, bool kF32>
+// kVec (u8 keys only): key rows and terrain rows start 16-byte aligned, and
+// every lane streams 16 posts per step with three 16-byte loads.
+template <int KMAX, bool kF32, bool kVec>
 __global__ __launch_bounds__(kFmThreads) void findmax_kernel(
     const void *__restrict__ keyp, int stride, const int16_t *__restrict__ z, int64_t nrows,
     int64_t ncols, int64_t ld, int grid_r, int grid_c, int k, int64_t *__restrict__ cand)
@@ -81,9 +84,40 @@ __global__ __launch_bounds__(kFmThreads) void findmax_kernel(
     }
     int64_t bw = lc1 - lc0, bh = lr1 - lr0;
     int64_t kc = kF32 ? (ncols + stride - 1) / stride : ncols;
-    // rows are walked by waves, columns by lanes: coalesced streaming
     int wave = tid >> 6, lane = tid & 63;
-    for (int64_t row = wave; row < bh; row += kFmThreads / 64) {
+    if (kVec) {
+        // threads walk the (row, 16-post chunk) pairs of the block; a post
+        // whose (count, elevation) is below the lane's k-th best is dropped
+        // before its full key is built
+        const int64_t cc0 = c0 & ~15ll;
+        const uint32_t nch = (uint32_t)((((c1 + 15) & ~15ll) - cc0) >> 4);
+        const uint32_t total = (uint32_t)bh * nch;
+        uint32_t thr = 0;  // top 24 bits of the lane's KMAX-th key
+        for (uint32_t i = tid; i < total; i += kFmThreads) {
+            const uint32_t row = i / nch, ch = i - row * nch;
+            const int64_t ly = r0 + row;
+            const int64_t cb = cc0 + ((int64_t)ch << 4);
+            const uint4 kv = *reinterpret_cast<const uint4 *>((const uint8_t *)keyp + ly * ncols + cb);
+            const uint4 za = *reinterpret_cast<const uint4 *>(z + ly * ld + cb);
+            const uint4 zb = *reinterpret_cast<const uint4 *>(z + ly * ld + cb + 8);
+            const uint32_t kw[4] = {kv.x, kv.y, kv.z, kv.w};
+            const uint32_t zw[8] = {za.x, za.y, za.z, za.w, zb.x, zb.y, zb.z, zb.w};
+#pragma unroll
+            for (int q = 0; q < 16; q++) {
+                const uint32_t c = (kw[q >> 2] >> ((q & 3) * 8)) & 0xFFu;
+                const uint32_t zz = ((zw[q >> 1] >> ((q & 1) * 16)) & 0xFFFFu) ^ 0x8000u;
+                const uint32_t hi = (c << 16) | zz;
+                const int64_t col = cb + q;
+                if (hi >= thr && col >= c0 && col < c1) {
+                    const uint64_t local = (uint64_t)row * (uint64_t)bw + (uint64_t)(col - c0);
+                    topk_insert<KMAX>(top, ((uint64_t)hi << 40) | (0xFFFFFFFFFFull - local));
+                    thr = (uint32_t)(top[KMAX - 1] >> 40);
+                }
+            }
+        }
+    }
+    // rows are walked by waves, columns by lanes: coalesced streaming
+    for (int64_t row = wave; !kVec && row < bh; row += kFmThreads / 64) {
         int64_t ly = lr0 + row;
         for (int64_t col = lane; col < bw; col += 64) {
             int64_t lx = lc0 + col;
@@ -185,14 +219,24 @@ extern "C" int siting_findmax(const void *key, int32_t key_type, int32_t key_str
     }
     hipStream_t s = as_stream(stream);
     dim3 g((unsigned)blocks), b(kFmThreads);
+    // 16-byte streaming when key rows (ncols bytes) and terrain rows (2*ld
+    // bytes) start 16-byte aligned and a block's chunk count fits 32 bits
+    const int64_t max_rows = (nrows + grid_r - 1) / grid_r + 1;
+    const int64_t max_chunks = ((ncols + grid_c - 1) / grid_c + 32) / 16;
+    const bool vec = key_type == SITING_KEY_U8 && ncols % 16 == 0 && ld % 8 == 0 &&
+                     (uintptr_t)key % 16 == 0 && (uintptr_t)z % 16 == 0 &&
+                     max_rows * max_chunks < ((int64_t)1 << 31);
 #define FM_LAUNCH(KM)                                                                          \
     do {                                                                                       \
-        if (key_type == SITING_KEY_U8)                                                         \
-            hipLaunchKernelGGL((findmax_kernel<KM, false>), g, b, 0, s, key, key_stride, z,    \
-                               nrows, ncols, ld, grid_r, grid_c, k, cand);                     \
+        if (vec)                                                                               \
+            hipLaunchKernelGGL((findmax_kernel<KM, false, true>), g, b, 0, s, key, key_stride, \
+                               z, nrows, ncols, ld, grid_r, grid_c, k, cand);                  \
+        else if (key_type == SITING_KEY_U8)                                                    \
+            hipLaunchKernelGGL((findmax_kernel<KM, false, false>), g, b, 0, s, key,            \
+                               key_stride, z, nrows, ncols, ld, grid_r, grid_c, k, cand);      \
         else                                                                                   \
-            hipLaunchKernelGGL((findmax_kernel<KM, true>), g, b, 0, s, key, key_stride, z,     \
-                               nrows, ncols, ld, grid_r, grid_c, k, cand);                     \
+            hipLaunchKernelGGL((findmax_kernel<KM, true, false>), g, b, 0, s, key, key_stride, \
+                               z, nrows, ncols, ld, grid_r, grid_c, k, cand);                  \
     } while (0)
     if (k <= 4)
         FM_LAUNCH(4);

@@ -60,7 +60,10 @@ def test_vix_strided_terrain(S, orc):
 
 # ------------------------------------------------------------ FINDMAX ------
 @pytest.mark.parametrize("shape,g_r,g_c,k", [((1000, 1000), 10, 10, 10), ((333, 517), 7, 3, 20),
-                                            ((97, 101), 97, 101, 1), ((250, 250), 4, 4, 32)])
+                                            ((97, 101), 97, 101, 1), ((250, 250), 4, 4, 32),
+                                            # 16-aligned rows (16-byte streaming), ragged blocks
+                                            ((480, 512), 7, 9, 20), ((130, 1024), 3, 5, 3),
+                                            ((64, 4096), 2, 3, 32)])
 def test_findmax_u8_parity(S, orc, shape, g_r, g_c, k):
     _say("findmax", shape, g_r, g_c, k)
     rng = np.random.default_rng(k)
