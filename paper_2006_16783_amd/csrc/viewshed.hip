@@ -182,6 +182,135 @@ __device__ __forceinline__ void sweep(const Src &src, int zs_u, int zs_v, uint32
     }
 }
 
+// 24-bit signed multiply-add (full rate): a * b + c with |a|, |b| < 2^23.
+__device__ __forceinline__ int mad_i24(int a, int b, int c)
+{
+    int r;
+    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+typedef const int16_t __attribute__((address_space(3))) lds_i16;
+__device__ __forceinline__ int lds_read_i16(int addr)
+{
+    return *reinterpret_cast<lds_i16 *>((uintptr_t)(uint32_t)addr);
+}
+
+// The common case of sweep(): terrain staged in LDS, narrow arithmetic.  The
+// same steps and comparisons in a cheaper form:
+//  * the minor remainder is kept as e = r - n in [-n, -1], so that a wrap is
+//    the carry of one add, and the interpolated terrain is
+//    n*z(t) = z1*n + (z1 - z0)*e;
+//  * the marked cell rounds up when 2r >= n, i.e. e >= -floor(n/2);
+//  * up to a bound ks (computed per ray) every marked cell lies inside the
+//    disk (k^2 + (q+1)^2 <= R^2), so those steps skip the disk test;
+//  * the receiver's line is tested as T*J + h_r*n*J >= hN*k with one
+//    multiply-add (h_r*n < 2^23 in narrow mode);
+//  * post offsets are LDS byte addresses (zq_addr: the observer's post).
+__device__ __forceinline__ void sweep_lds_narrow(int zq_addr, int zp, uint32_t *bm, int P0,
+                                                 int bu, int bv, int du, int dv, int R2, int E,
+                                                 int h_r)
+{
+    const bool umaj = du >= dv;
+    const int n = umaj ? du : dv, mn = umaj ? dv : du;
+    const int zs_maj = umaj ? 2 : 2 * zp, zs_min = umaj ? 2 * zp : 2;
+    const int bs_maj = umaj ? bu : bv, bs_min = umaj ? bv : bu;
+    const int nEn = -E * n;
+    const int hrn = h_r * n;
+    const int nhalf = -(n >> 1);
+    // step 1 (no horizon yet)
+    int e = mn - n, q = 0;
+    if (e >= 0) {  // the diagonal: mn == n
+        e -= n;
+        q = 1;
+    }
+    {
+        const int m = q + (e >= nhalf ? 1 : 0);
+        if (1 + m * m > R2)
+            return;
+    }
+    int zi = zq_addr + zs_maj + q * zs_min;
+    int bq = P0 + bs_maj + q * bs_min;
+    int T;
+    {
+        const int z0 = lds_read_i16(zi), z1 = lds_read_i16(zi + zs_min);
+        T = mad_i24(z1 - z0, e, mad_i24(z1, n, nEn));
+        const int bp = bq + (e >= nhalf ? bs_min : 0);
+        atomicOr(&bm[bp >> 5], 1u << (bp & 31));
+    }
+    int hN = T, hJ = 1, B = T;
+    // ks: the last step whose marked cell is surely inside the disk, from
+    // k^2 + (k*mn/n + 1)^2 <= R^2, then checked exactly
+    int ks;
+    {
+        const float a = (float)mn / (float)n, c = 1.0f + a * a;
+        const float root = (-a + sqrtf(a * a + c * (float)(R2 - 1))) / c;
+        ks = (int)root;
+        ks = ks < 1 ? 1 : ks > n ? n : ks;
+        while (ks > 1) {
+            const int qq = (int)(((long long)ks * mn) / n) + 1;
+            if ((long long)ks * ks + (long long)qq * qq <= R2)
+                break;
+            ks--;
+        }
+    }
+    uint32_t eu = (uint32_t)e;
+    int k = 2;
+    for (; k <= ks; k++) {
+        uint32_t e1;
+        const bool w = __builtin_add_overflow(eu, (uint32_t)mn, &e1);
+        eu = w ? e1 - (uint32_t)n : e1;
+        zi += zs_maj + (w ? zs_min : 0);
+        bq += bs_maj + (w ? bs_min : 0);
+        const int ee = (int)eu;
+        const int z0 = lds_read_i16(zi), z1 = lds_read_i16(zi + zs_min);
+        const int Tk = mad_i24(z1 - z0, ee, mad_i24(z1, n, nEn));
+        B += hN;
+        const int PT = __mul24(Tk, hJ);
+        const int PV = mad_i24(hrn, hJ, PT);
+        const int bp = bq + (ee >= nhalf ? bs_min : 0);
+        if (PV >= B)
+            atomicOr(&bm[bp >> 5], 1u << (bp & 31));
+        if (PT > B) {
+            hN = Tk;
+            hJ = k;
+            B = __mul24(Tk, k);
+        }
+    }
+    if (k > n)
+        return;
+    // the remaining steps test the disk: q from the remainder, k^2 tracked
+    q = (int)(((long long)(k - 1) * mn) / n);
+    int k2 = (k - 1) * (k - 1);
+    for (; k <= n; k++) {
+        uint32_t e1;
+        const bool w = __builtin_add_overflow(eu, (uint32_t)mn, &e1);
+        eu = w ? e1 - (uint32_t)n : e1;
+        zi += zs_maj + (w ? zs_min : 0);
+        bq += bs_maj + (w ? bs_min : 0);
+        q += w ? 1 : 0;
+        k2 += 2 * k - 1;
+        const int ee = (int)eu;
+        const int up = ee >= nhalf ? 1 : 0;
+        const int m = q + up;
+        if (k2 + __mul24(m, m) > R2)
+            break;
+        const int z0 = lds_read_i16(zi), z1 = lds_read_i16(zi + zs_min);
+        const int Tk = mad_i24(z1 - z0, ee, mad_i24(z1, n, nEn));
+        B += hN;
+        const int PT = __mul24(Tk, hJ);
+        const int PV = mad_i24(hrn, hJ, PT);
+        const int bp = bq + (up ? bs_min : 0);
+        if (PV >= B)
+            atomicOr(&bm[bp >> 5], 1u << (bp & 31));
+        if (PT > B) {
+            hN = Tk;
+            hJ = k;
+            B = __mul24(Tk, k);
+        }
+    }
+}
+
 // LDS layout helpers (bytes), shared by host sizing and the kernel.
 __host__ __device__ __forceinline__ int bm_pitch_dw(int rmax)
 {
@@ -233,6 +362,9 @@ __global__ void viewshed_kernel(const int16_t *__restrict__ z, int64_t nrows, in
     uint32_t *bm = lds;
     int16_t *zq = reinterpret_cast<int16_t *>(lds + bm_bytes(rmax) / 4);
     const int zp = zq_pitch(stage_rmax);
+    // LDS byte address of the staged quadrant's origin (the observer's post)
+    const int zq_addr =
+        (int)(uint32_t)(uintptr_t)(const __attribute__((address_space(3))) int16_t *)zq;
     const int BPdw = bm_pitch_dw(rmax);
     const int BP = BPdw * 32;
 
@@ -329,7 +461,7 @@ __global__ void viewshed_kernel(const int16_t *__restrict__ z, int64_t nrows, in
                     int du, dv;
                     ray_target(Q, rho, du, dv);
                     if (narrow)
-                        sweep<true, false>(src, 1, zp, bm, P0, Q.bu, Q.bv, du, dv, R2, E, o.h_r);
+                        sweep_lds_narrow(zq_addr, zp, bm, P0, Q.bu, Q.bv, du, dv, R2, E, o.h_r);
                     else
                         sweep<false, false>(src, 1, zp, bm, P0, Q.bu, Q.bv, du, dv, R2, E, o.h_r);
                 }
