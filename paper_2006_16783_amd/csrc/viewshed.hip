@@ -247,9 +247,10 @@ __device__ __forceinline__ void sweep_lds_narrow(int zq_addr, int zp, uint32_t *
         const float root = (-a + sqrtf(a * a + c * (float)(R2 - 1))) / c;
         ks = (int)root;
         ks = ks < 1 ? 1 : ks > n ? n : ks;
+        // (every product < 2^31: ks, mn <= n <= R <= 16383)
         while (ks > 1) {
-            const int qq = (int)(((long long)ks * mn) / n) + 1;
-            if ((long long)ks * ks + (long long)qq * qq <= R2)
+            const int qq = (int)((uint32_t)(ks * mn) / (uint32_t)n) + 1;
+            if (ks * ks + qq * qq <= R2)
                 break;
             ks--;
         }
@@ -280,7 +281,7 @@ __device__ __forceinline__ void sweep_lds_narrow(int zq_addr, int zp, uint32_t *
     if (k > n)
         return;
     // the remaining steps test the disk: q from the remainder, k^2 tracked
-    q = (int)(((long long)(k - 1) * mn) / n);
+    q = (int)((uint32_t)((k - 1) * mn) / (uint32_t)n);
     int k2 = (k - 1) * (k - 1);
     for (; k <= n; k++) {
         uint32_t e1;
@@ -457,7 +458,12 @@ __global__ void viewshed_kernel(const int16_t *__restrict__ z, int64_t nrows, in
                 bool narrow = D * R < (1ll << 23) && D * R * R < (1ll << 31);
                 LdsSrc src{zq};
                 const int nrays = Q.eu + Q.ev;
-                for (int rho = tid; rho < nrays; rho += nthreads) {
+                // threads take the boundary cells from both ends inwards: the
+                // near-axis rays (longest) fill the full wavefronts, and the
+                // partial last one gets the near-diagonal rays, which leave
+                // the disk first
+                for (int t = tid; t < nrays; t += nthreads) {
+                    const int rho = (t & 1) ? nrays - 1 - (t >> 1) : (t >> 1);
                     int du, dv;
                     ray_target(Q, rho, du, dv);
                     if (narrow)
