@@ -8,17 +8,19 @@
 //   key[i]   (gain bound << 32) | (2^32-1 - i): one 64-bit max gives the
 //            largest bound with ties to the smallest index
 //   fresh[i] the round in which key[i] was last computed exactly
-//   bmax[b]  max of key[] over block b of 1024 candidates (LDS)
-// One persistent workgroup of 1024 threads runs every round.  If the global
-// top key is fresh it is exactly the plain greedy argmax and is taken (its
-// window ORed into C).  Otherwise wavefronts re-evaluate in parallel:
-// wavefront w owns the blocks b = w (mod 16) and recomputes the top
-// candidate of its best block, popcount(V & ~C) over the window, then that
-// block's maximum.  The first stale pass of a round re-evaluates only the
-// global top, with the whole workgroup (one window word per thread); the
-// k-th later pass involves the 2^k wavefronts with the best tops (at most
-// 16).  The global top is always among them, so every pass makes progress;
-// sparse candidate sets need one re-evaluation per round, dense ones (where
+//   bmax[b]  max of key[] over block b of 1024 candidates, with the round
+//            stamp of that maximum (LDS)
+// One persistent workgroup of 1024 threads runs every round.  The top key
+// and the best key outside the top's block come from the block maxima.  The
+// first pass of a round loads the top's window, its cumulative words and the
+// keys of its block together (one window word and one key per thread); a
+// stale top is re-evaluated, popcount(V & ~C), and taken at once if its exact
+// key still exceeds every other key (the stated bound: gains only shrink), in
+// which case its window is ORed into C from the words already loaded.  If it
+// does not, later passes re-evaluate in parallel: the k-th involves the 2^k
+// wavefronts with the best tops (at most 16), wavefront w owning the blocks
+// b = w (mod 16).  The global top is always among them, so every pass makes
+// progress; sparse candidate sets need one pass per round, dense ones (where
 // a selection leaves many stale neighbours on top) converge in a few wide
 // passes.
 #include <algorithm>
@@ -113,7 +115,8 @@ __global__ __launch_bounds__(256) void greedy_init(const uint64_t *__restrict__ 
 }
 
 // gain of candidate j against C: popcount(V_j & ~C) over its window, one
-// wavefront (result in every lane)
+// wavefront (result in every lane); eight words per lane are loaded before
+// any is used, so a window costs a few memory round trips
 __device__ __forceinline__ uint64_t wave_gain(const uint64_t *__restrict__ bitmaps,
                                               const int64_t *__restrict__ offsets,
                                               const siting_observer &o, int64_t j, int64_t nrows,
@@ -124,21 +127,58 @@ __device__ __forceinline__ uint64_t wave_gain(const uint64_t *__restrict__ bitma
     const uint64_t *v = bitmaps + offsets[j];
     const int words = w.rows * w.nw;
     uint64_t cnt = 0;
-    for (int e = lane; e < words; e += 64) {
-        const int row = e / w.nw, c = e - row * w.nw;
-        cnt += __popcll(v[e] & ~C[(w.ylo + row) * W + w.w0 + c]);
+    for (int e0 = 0; e0 < words; e0 += 8 * 64) {
+        uint64_t vv[8], cc[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const int e = e0 + u * 64 + lane;
+            vv[u] = 0;
+            cc[u] = 0;
+            if (e < words) {
+                const int row = e / w.nw, c = e - row * w.nw;
+                vv[u] = v[e];
+                cc[u] = C[(w.ylo + row) * W + w.w0 + c];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; u++)
+            cnt += __popcll(vv[u] & ~cc[u]);
     }
     return wave_sum_u64(cnt);
 }
 
-// max key of block b, one wavefront (result in every lane)
-__device__ __forceinline__ uint64_t wave_block_max(const uint64_t *key, int64_t n, int b, int lane)
+// max key of block b and that key's stamp, one wavefront (results in every
+// lane); the key of candidate `ov` (if in the block) is taken as `ok` with
+// stamp `of` instead of its stored value
+__device__ __forceinline__ void wave_block_max(const uint64_t *key, const int32_t *fresh, int64_t n,
+                                               int b, int lane, int64_t ov, uint64_t ok,
+                                               int32_t of, uint64_t &best, int32_t &bfr)
 {
     uint64_t v = 0;
-    for (int64_t j = (int64_t)b * kGreedyBlock + lane; j < n && j < (int64_t)(b + 1) * kGreedyBlock;
-         j += 64)
-        v = key[j] > v ? key[j] : v;
-    return wave_max_u64(v);
+    int32_t f = 0;
+    const int64_t j0 = (int64_t)b * kGreedyBlock + lane;
+    uint64_t kk[kGreedyBlock / 64];
+    int32_t ff[kGreedyBlock / 64];
+#pragma unroll
+    for (int u = 0; u < kGreedyBlock / 64; u++) {
+        const int64_t j = j0 + u * 64;
+        kk[u] = 0;
+        ff[u] = 0;
+        if (j < n) {
+            kk[u] = j == ov ? ok : key[j];
+            ff[u] = j == ov ? of : fresh[j];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kGreedyBlock / 64; u++) {
+        if (kk[u] > v) {
+            v = kk[u];
+            f = ff[u];
+        }
+    }
+    best = wave_max_u64(v);
+    const uint64_t owner = __ballot(v == best && best != 0);
+    bfr = __shfl(f, owner ? __ffsll((long long)owner) - 1 : 0, 64);
 }
 
 __global__ __launch_bounds__(kGreedyThreads) void greedy_run(
@@ -147,37 +187,42 @@ __global__ __launch_bounds__(kGreedyThreads) void greedy_run(
     int32_t max_obs, int64_t target, uint64_t *C, int64_t *__restrict__ selected,
     int64_t *__restrict__ gains, int32_t *__restrict__ nselected, uint64_t *key, int32_t *fresh)
 {
+    // block maxima of the keys and the round stamps of those maxima
     extern __shared__ uint64_t bmax[];
-    __shared__ uint64_t s_red[kGreedyWaves];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t W = (ncols + 63) >> 6;
     const int nblocks = (int)((n + kGreedyBlock - 1) / kGreedyBlock);
+    int32_t *bfr = reinterpret_cast<int32_t *>(bmax + nblocks);
+    __shared__ uint64_t s_a[kGreedyWaves], s_b[kGreedyWaves];
+    __shared__ int32_t s_f;
 
-    // workgroup-wide reductions (result in every thread)
-    auto wg_reduce = [&](uint64_t v, bool is_max) -> uint64_t {
-        v = is_max ? wave_max_u64(v) : wave_sum_u64(v);
+    // workgroup sum of a and max of b in one exchange (results in every
+    // thread)
+    auto wg_sum_max = [&](uint64_t a, uint64_t b, uint64_t &sa, uint64_t &mb) {
+        a = wave_sum_u64(a);
+        b = wave_max_u64(b);
         __syncthreads();
-        if (lane == 0)
-            s_red[wave] = v;
+        if (lane == 0) {
+            s_a[wave] = a;
+            s_b[wave] = b;
+        }
         __syncthreads();
-        uint64_t r = is_max ? 0 : 0;
-        for (int w2 = 0; w2 < kGreedyWaves; w2++)
-            r = is_max ? (s_red[w2] > r ? s_red[w2] : r) : r + s_red[w2];
-        __syncthreads();
-        return r;
-    };
-    // workgroup-wide refresh of bmax[b] (one key per thread)
-    auto wg_refresh = [&](int b) {
-        const int64_t j = (int64_t)b * kGreedyBlock + tid;
-        const uint64_t v = wg_reduce(j < n ? key[j] : 0, true);
-        if (tid == 0)
-            bmax[b] = v;
+        sa = 0;
+        mb = 0;
+        for (int w2 = 0; w2 < kGreedyWaves; w2++) {
+            sa += s_a[w2];
+            mb = s_b[w2] > mb ? s_b[w2] : mb;
+        }
     };
 
     for (int b = wave; b < nblocks; b += kGreedyWaves) {
-        const uint64_t v = wave_block_max(key, n, b, lane);
-        if (lane == 0)
+        uint64_t v;
+        int32_t f;
+        wave_block_max(key, fresh, n, b, lane, -1, 0, 0, v, f);
+        if (lane == 0) {
             bmax[b] = v;
+            bfr[b] = f;
+        }
     }
     __syncthreads();
 
@@ -185,98 +230,150 @@ __global__ __launch_bounds__(kGreedyThreads) void greedy_run(
     int64_t covered = 0;
     int pass = 0;
     while (t < max_obs && covered < target) {
-        // ---- global top key: every wavefront takes the max over its blocks
-        // (kept for the re-evaluation below), then the workgroup max
-        uint64_t mine = 0;
-        int myb = -1;
-        // lanes stride over this wavefront's blocks
+        // ---- global top key and the best key outside its block: every
+        // wavefront takes the two largest of its blocks, then the workgroup
+        uint64_t m1 = 0, m2 = 0;
+        int b1 = -1;
         for (int b = wave + kGreedyWaves * lane; b < nblocks; b += kGreedyWaves * 64) {
             const uint64_t v = bmax[b];
-            if (v > mine) {
-                mine = v;
-                myb = b;
+            if (v > m1) {
+                m2 = m1;
+                m1 = v;
+                b1 = b;
+            } else if (v > m2) {
+                m2 = v;
             }
         }
-        // wavefront argmax (keys are unique, so the owner lane is unique)
-        const uint64_t wmax = wave_max_u64(mine);
-        const uint64_t owner = __ballot(mine == wmax && wmax != 0);
-        const int wb = __shfl(myb, owner ? __ffsll((long long)owner) - 1 : 0, 64);
-        if (lane == 0)
-            s_red[wave] = wmax;
+        const uint64_t wmax = wave_max_u64(m1);
+        const uint64_t owner = __ballot(m1 == wmax && wmax != 0);
+        const int ol = owner ? __ffsll((long long)owner) - 1 : 0;
+        const int wb = __shfl(b1, ol, 64);
+        // the wavefront's second: the owner's own second or another lane's first
+        const uint64_t wsec = wave_max_u64(lane == ol ? m2 : m1);
+        if (lane == 0) {
+            s_a[wave] = wmax;
+            s_b[wave] = wsec;
+        }
         __syncthreads();
-        uint64_t top = 0;
+        uint64_t top = 0, second = 0;
         int rank = 0;  // wavefronts holding a larger top than this one
+        int tw = 0;
         for (int w2 = 0; w2 < kGreedyWaves; w2++) {
-            const uint64_t v = s_red[w2];
-            top = v > top ? v : top;
+            const uint64_t v = s_a[w2];
+            if (v > top) {
+                top = v;
+                tw = w2;
+            }
             rank += v > wmax;
+        }
+        for (int w2 = 0; w2 < kGreedyWaves; w2++) {
+            const uint64_t v = w2 == tw ? s_b[w2] : s_a[w2];
+            second = v > second ? v : second;
         }
         const int64_t i = (int64_t)(0xFFFFFFFFull - (top & 0xFFFFFFFFull));
         const uint64_t g = top >> 32;
         if (top == 0 || i >= n)
             break;  // unreachable with n >= 1
-        const int32_t fr = fresh[i];
-        __syncthreads();  // every thread has read s_red and fresh[i]
-        if (fr == t) {
-            if (g == 0)
+        const int bi = (int)(i / kGreedyBlock);
+        const int32_t fr = bfr[bi];
+        __syncthreads();  // every thread has read s_a, s_b and bfr
+        if (fr == t || pass == 0) {
+            // Re-evaluate the top if it is stale (the whole workgroup, one
+            // window word per thread), and take it if it is fresh or stays
+            // above every other key.  The window, the cumulative words and the
+            // top's block of keys are loaded together.
+            const bool stale = fr != t;
+            if (!stale && g == 0)
                 break;
-            const Win w = window_of(obs[i], nrows, ncols);
-            const uint64_t *v = bitmaps + offsets[i];
-            for (int e = tid; e < w.rows * w.nw; e += kGreedyThreads) {
-                const int row = e / w.nw, c = e - row * w.nw;
-                C[(w.ylo + row) * W + w.w0 + c] |= v[e];
-            }
-            if (tid == 0) {
-                selected[t] = i;
-                gains[t] = (int64_t)g;
-                key[i] = 0xFFFFFFFFull - (uint64_t)i;  // gains nothing from now on
-                fresh[i] = t + 1;
-            }
-            __syncthreads();
-            wg_refresh((int)(i / kGreedyBlock));
-            covered += (int64_t)g;
-            t++;
-            pass = 0;
-        } else if (pass == 0) {
-            // first stale pass of a round: the whole workgroup re-evaluates
-            // the global top (one word per thread), then refreshes its block
             const siting_observer o = obs[i];
+            const bool valid = obs_ok(o, nrows, ncols);
+            const int64_t j = (int64_t)bi * kGreedyBlock + tid;
+            const uint64_t kj = j < n ? key[j] : 0;
+            const int32_t fj = j < n ? fresh[j] : 0;
+            Win w{0, 0, 0, 0};
+            const uint64_t *v = bitmaps;
+            if (valid) {
+                w = window_of(o, nrows, ncols);
+                v = bitmaps + offsets[i];
+            }
+            const int words = w.rows * w.nw;
+            // this thread's first window word stays in registers for the OR
+            uint64_t v0 = 0, c0 = 0;
             uint64_t cnt = 0;
-            if (obs_ok(o, nrows, ncols)) {
-                const Win w = window_of(o, nrows, ncols);
-                const uint64_t *v = bitmaps + offsets[i];
-                for (int e = tid; e < w.rows * w.nw; e += kGreedyThreads) {
+            for (int e = tid; e < words; e += kGreedyThreads) {
+                const int row = e / w.nw, c = e - row * w.nw;
+                const uint64_t ve = v[e], ce = C[(w.ylo + row) * W + w.w0 + c];
+                if (e == tid) {
+                    v0 = ve;
+                    c0 = ce;
+                }
+                cnt += __popcll(ve & ~ce);
+            }
+            // one exchange: the exact gain (when stale) and the largest key of
+            // the top's block other than the top's own
+            const uint64_t kj_ex = j == i ? 0 : kj;
+            uint64_t gsum, bo;
+            wg_sum_max(stale ? cnt : 0, kj_ex, gsum, bo);
+            const uint64_t gain = stale ? gsum : g;
+            const uint64_t nk = (gain << 32) | (0xFFFFFFFFull - (uint64_t)i);
+            // lazy greedy: a fresh gain at least every other key (stale or
+            // not) is the plain greedy choice; keys are unique
+            const bool take = gain > 0 && (!stale || (nk > second && nk > bo));
+            // after this pass: nk for i, or a zero gain once i is taken
+            const uint64_t ki = take ? (0xFFFFFFFFull - (uint64_t)i) : nk;
+            const int32_t fi = take ? t + 1 : t;
+            const uint64_t bm2 = ki > bo ? ki : bo;
+            if (bm2 == bo && kj_ex == bo && bo != 0)
+                s_f = fj;  // the block's new maximum is another candidate's
+            if (tid == 0 && bm2 == ki)
+                s_f = fi;
+            if (take) {
+                for (int e = tid; e < words; e += kGreedyThreads) {
                     const int row = e / w.nw, c = e - row * w.nw;
-                    cnt += __popcll(v[e] & ~C[(w.ylo + row) * W + w.w0 + c]);
+                    uint64_t *ce = &C[(w.ylo + row) * W + w.w0 + c];
+                    *ce = e == tid ? (c0 | v0) : (*ce | v[e]);
                 }
             }
-            cnt = wg_reduce(cnt, false);
-            if (tid == 0) {
-                key[i] = (cnt << 32) | (0xFFFFFFFFull - (uint64_t)i);
-                fresh[i] = t;
-            }
             __syncthreads();
-            wg_refresh((int)(i / kGreedyBlock));
-            pass = 1;
+            if (tid == 0) {
+                key[i] = ki;
+                fresh[i] = fi;
+                bmax[bi] = bm2;
+                bfr[bi] = s_f;
+                if (take) {
+                    selected[t] = i;
+                    gains[t] = (int64_t)gain;
+                }
+            }
+            if (take) {
+                covered += (int64_t)gain;
+                t++;
+                pass = 0;
+            } else {
+                pass = 1;
+            }
         } else {
             // later stale passes: the k-th re-evaluates the tops of the 2^k
             // best wavefronts in parallel, one wavefront each (up to 16)
             const bool go = wmax != 0 && rank < (1 << pass);
             pass = pass < 4 ? pass + 1 : 4;
             // ---- this wavefront re-evaluates the top of its best block
-            const int64_t j = (int64_t)(0xFFFFFFFFull - (wmax & 0xFFFFFFFFull));
-            if (go && fresh[j] != t) {
-                const siting_observer o = obs[j];
+            const int64_t jj = (int64_t)(0xFFFFFFFFull - (wmax & 0xFFFFFFFFull));
+            if (go && bfr[wb] != t) {
+                const siting_observer o = obs[jj];
                 uint64_t gj = 0;
                 if (obs_ok(o, nrows, ncols))
-                    gj = wave_gain(bitmaps, offsets, o, j, nrows, ncols, C, W, lane);
+                    gj = wave_gain(bitmaps, offsets, o, jj, nrows, ncols, C, W, lane);
+                const uint64_t nkj = (gj << 32) | (0xFFFFFFFFull - (uint64_t)jj);
+                uint64_t bv;
+                int32_t bf;
+                wave_block_max(key, fresh, n, wb, lane, jj, nkj, t, bv, bf);
                 if (lane == 0) {
-                    key[j] = (gj << 32) | (0xFFFFFFFFull - (uint64_t)j);
-                    fresh[j] = t;
-                }
-                const uint64_t bv = wave_block_max(key, n, wb, lane);
-                if (lane == 0)
+                    key[jj] = nkj;
+                    fresh[jj] = t;
                     bmax[wb] = bv;
+                    bfr[wb] = bf;
+                }
             }
         }
         __syncthreads();
@@ -320,7 +417,7 @@ extern "C" int siting_greedy(const uint64_t *bitmaps, const int64_t *offsets,
     }
     const int64_t nblocks = (n + kGreedyBlock - 1) / kGreedyBlock;
     if (nblocks > kGreedyMaxBlocks ||
-        nblocks * 8 > kernel_max_dynamic_lds(reinterpret_cast<const void *>(&greedy_run))) {
+        nblocks * 12 > kernel_max_dynamic_lds(reinterpret_cast<const void *>(&greedy_run))) {
         set_error("%s: %lld candidates exceed the supported maximum", fn, (long long)n);
         return SITING_E_UNSUPPORTED;
     }
@@ -339,7 +436,7 @@ extern "C" int siting_greedy(const uint64_t *bitmaps, const int64_t *offsets,
                        offsets, obs, n, nrows, ncols, key, fresh);
     if ((rc = check_launch("greedy_init")) != SITING_OK)
         return rc;
-    hipLaunchKernelGGL(greedy_run, dim3(1), dim3(kGreedyThreads), (size_t)nblocks * 8, s, bitmaps,
+    hipLaunchKernelGGL(greedy_run, dim3(1), dim3(kGreedyThreads), (size_t)nblocks * 12, s, bitmaps,
                        offsets, obs, n, nrows, ncols, max_obs, target_cells, cumulative, selected,
                        gains, nselected, key, fresh);
     return check_launch("greedy_run");
