@@ -33,6 +33,11 @@ constexpr int OW1 = 0, OB1 = 256, OW2 = 272, OB2 = 2576, OW3 = 2592, OB3 = 7200,
               OBFC = 7264, NPARAMS = 7265;
 constexpr int kPatch = 64;
 constexpr int kFwdWaves = 4;
+// LDS pitch of one activation position: 16 channels padded to 18 bf16
+// (36 bytes), so that the 4-channel fragments of positions two apart, which
+// the 3x3 stride-2 layers read side by side, fall in different banks
+constexpr int kPosPitch = 18;
+constexpr int kWaveLdsElems = 256 * kPosPitch + 64 * kPosPitch;
 
 __device__ __forceinline__ short bf16_bits(float f)
 {
@@ -59,6 +64,19 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// 4 consecutive bf16 at a 4-byte aligned LDS address (two dword reads)
+__device__ __forceinline__ s4 lds_frag(const uint16_t *p)
+{
+    const uint32_t *q = reinterpret_cast<const uint32_t *>(p);
+    const uint32_t u0 = q[0], u1 = q[1];
+    s4 r;
+    r.x = (short)(u0 & 0xFFFFu);
+    r.y = (short)(u0 >> 16);
+    r.z = (short)(u1 & 0xFFFFu);
+    r.w = (short)(u1 >> 16);
+    return r;
 }
 
 __device__ __forceinline__ f4 mfma(s4 a, s4 b, f4 c)
@@ -94,9 +112,9 @@ __global__ __launch_bounds__(64 * kFwdWaves) void cnn_fwd_kernel(FwdArgs A)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lo = lane & 15, hi = lane >> 4;
     // per-wave activations: H1 [256 pos][16 ch] bf16, H2 [64 pos][16 ch]
-    uint16_t *H1 = reinterpret_cast<uint16_t *>(smem) + wave * (256 * 16 + 64 * 16);
-    uint16_t *H2 = H1 + 256 * 16;
-    int16_t *tile = reinterpret_cast<int16_t *>(smem + kFwdWaves * (256 * 16 + 64 * 16) * 2);
+    uint16_t *H1 = reinterpret_cast<uint16_t *>(smem) + wave * kWaveLdsElems;
+    uint16_t *H2 = H1 + 256 * kPosPitch;
+    int16_t *tile = reinterpret_cast<int16_t *>(smem + kFwdWaves * kWaveLdsElems * 2);
 
     // weights as B fragments (bf16) and per-lane biases
     const float *p = A.params;
@@ -216,7 +234,7 @@ __global__ __launch_bounds__(64 * kFwdWaves) void cnn_fwd_kernel(FwdArgs A)
             for (int i = 0; i < 4; i++) {
                 const int ox = 4 * hi + i;
                 const uint16_t h = (uint16_t)bf16_bits(fmaxf(c[i] + b1, 0.f));
-                H1[(oy * 16 + ox) * 16 + lo] = h;
+                H1[(oy * 16 + ox) * kPosPitch + lo] = h;
                 if (kTrain)
                     A.H1st[(pid * 256 + oy * 16 + ox) * 16 + lo] = h;
             }
@@ -233,8 +251,7 @@ __global__ __launch_bounds__(64 * kFwdWaves) void cnn_fwd_kernel(FwdArgs A)
             for (int tap = 0; tap < 9; tap++) {
                 const int ky = tap / 3, kx = tap - ky * 3;
                 // 4 consecutive channels: one 8-byte LDS read
-                const s4 a = *reinterpret_cast<const s4 *>(
-                    H1 + ((2 * oy + ky) * 16 + (2 * ox + kx)) * 16 + 4 * hi);
+                const s4 a = lds_frag(H1 + ((2 * oy + ky) * 16 + (2 * ox + kx)) * kPosPitch + 4 * hi);
                 c = mfma(a, bw2[tap], c);
             }
 #pragma unroll
@@ -242,7 +259,7 @@ __global__ __launch_bounds__(64 * kFwdWaves) void cnn_fwd_kernel(FwdArgs A)
                 const int pos = 16 * t + 4 * hi + i;
                 if (pos < 49) {
                     const uint16_t h = (uint16_t)bf16_bits(fmaxf(c[i] + b2, 0.f));
-                    H2[pos * 16 + lo] = h;
+                    H2[pos * kPosPitch + lo] = h;
                     if (kTrain)
                         A.H2st[(pid * 49 + pos) * 16 + lo] = h;
                 }
@@ -257,8 +274,7 @@ __global__ __launch_bounds__(64 * kFwdWaves) void cnn_fwd_kernel(FwdArgs A)
 #pragma unroll
             for (int tap = 0; tap < 9; tap++) {
                 const int ky = tap / 3, kx = tap - ky * 3;
-                const s4 a = *reinterpret_cast<const s4 *>(
-                    H2 + ((2 * oy + ky) * 7 + (2 * ox + kx)) * 16 + 4 * hi);
+                const s4 a = lds_frag(H2 + ((2 * oy + ky) * 7 + (2 * ox + kx)) * kPosPitch + 4 * hi);
                 c3[0] = mfma(a, bw3[tap][0], c3[0]);
                 c3[1] = mfma(a, bw3[tap][1], c3[1]);
             }
@@ -652,7 +668,7 @@ extern "C" int siting_cnn_forward(const float *params, const int16_t *z, int64_t
     a.centres = centres; a.nposts = B;
     a.Pst = w.P; a.H1st = w.H1; a.H2st = w.H2; a.H3st = w.H3; a.gst = w.g; a.yst = w.y;
     hipStream_t s = as_stream(stream);
-    const size_t lds = kFwdWaves * ((256 * 16 + 64 * 16) * 2 + kPatch * kPatch * 2);
+    const size_t lds = kFwdWaves * (kWaveLdsElems * 2 + kPatch * kPatch * 2);
     const int64_t grid = std::min<int64_t>((B + kFwdWaves - 1) / kFwdWaves,
                                            (int64_t)device_cus() * 8);
     hipLaunchKernelGGL(cnn_fwd_kernel<true>, dim3((unsigned)grid), dim3(64 * kFwdWaves), lds, s, a);
@@ -797,7 +813,7 @@ extern "C" int siting_cnn_score_terrain(const float *params, const int16_t *z, i
     a.blocks_c = (a.lat_c + a.BL - 1) / a.BL;
     a.score = score;
     const int tw = a.BL * stride + kPatch - 1;
-    const size_t lds = kFwdWaves * (256 * 16 + 64 * 16) * 2 + (size_t)tw * tw * 2;
+    const size_t lds = kFwdWaves * kWaveLdsElems * 2 + (size_t)tw * tw * 2;
     if ((int64_t)lds > kernel_max_dynamic_lds(reinterpret_cast<const void *>(&cnn_fwd_kernel<false>))) {
         set_error("%s: tile does not fit in LDS", fn);
         return SITING_E_UNSUPPORTED;
