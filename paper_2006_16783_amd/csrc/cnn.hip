@@ -241,27 +241,40 @@ __global__ __launch_bounds__(64 * kFwdWaves) void cnn_fwd_kernel(FwdArgs A)
         }
         wave_lds_sync();
         // ---- conv2: 49 output positions in 4 row tiles, 9 taps of 16 channels
-#pragma unroll 1
-        for (int t = 0; t < 4; t++) {
-            int m = 16 * t + lo;
-            m = m > 48 ? 48 : m;
-            const int oy = m / 7, ox = m - oy * 7;
-            f4 c = {0.f, 0.f, 0.f, 0.f};
+        {
+            // the four row tiles' accumulations interleaved (independent
+            // MFMA chains)
+            int ty[4], tx[4];
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                int m = 16 * t + lo;
+                m = m > 48 ? 48 : m;
+                ty[t] = m / 7;
+                tx[t] = m - ty[t] * 7;
+            }
+            f4 c[4] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f},
+                       {0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
             for (int tap = 0; tap < 9; tap++) {
                 const int ky = tap / 3, kx = tap - ky * 3;
-                // 4 consecutive channels: one 8-byte LDS read
-                const s4 a = lds_frag(H1 + ((2 * oy + ky) * 16 + (2 * ox + kx)) * kPosPitch + 4 * hi);
-                c = mfma(a, bw2[tap], c);
+#pragma unroll
+                for (int t = 0; t < 4; t++) {
+                    // 4 consecutive channels of one input position
+                    const s4 a = lds_frag(H1 + ((2 * ty[t] + ky) * 16 + (2 * tx[t] + kx)) * kPosPitch + 4 * hi);
+                    c[t] = mfma(a, bw2[tap], c[t]);
+                }
             }
 #pragma unroll
-            for (int i = 0; i < 4; i++) {
-                const int pos = 16 * t + 4 * hi + i;
-                if (pos < 49) {
-                    const uint16_t h = (uint16_t)bf16_bits(fmaxf(c[i] + b2, 0.f));
-                    H2[pos * kPosPitch + lo] = h;
-                    if (kTrain)
-                        A.H2st[(pid * 49 + pos) * 16 + lo] = h;
+            for (int t = 0; t < 4; t++) {
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    const int pos = 16 * t + 4 * hi + i;
+                    if (pos < 49) {
+                        const uint16_t h = (uint16_t)bf16_bits(fmaxf(c[t][i] + b2, 0.f));
+                        H2[pos * kPosPitch + lo] = h;
+                        if (kTrain)
+                            A.H2st[(pid * 49 + pos) * 16 + lo] = h;
+                    }
                 }
             }
         }
