@@ -147,13 +147,34 @@ __global__ __launch_bounds__(64 * kFwdWaves) void cnn_fwd_kernel(FwdArgs A)
         tw = th = A.BL * A.stride + kPatch - 1;
         ty0 = bi * A.BL * A.stride - kPatch / 2;
         tx0 = bj * A.BL * A.stride - kPatch / 2;
-        // stage the clamped tile once for the whole workgroup
-        for (int e = tid; e < th * tw; e += 64 * kFwdWaves) {
-            int r = e / tw, c = e - r * tw;
-            int64_t gy = ty0 + r, gx = tx0 + c;
-            gy = gy < 0 ? 0 : gy > A.nrows - 1 ? A.nrows - 1 : gy;
-            gx = gx < 0 ? 0 : gx > A.ncols - 1 ? A.ncols - 1 : gx;
-            tile[e] = A.z[gy * A.ld + gx];
+        // stage the clamped tile once for the whole workgroup: rows by
+        // wavefronts, columns by lanes, four rows' loads in flight at once
+        for (int r0 = wave; r0 < th; r0 += 4 * kFwdWaves) {
+            int16_t v[4][4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int r = r0 + u * kFwdWaves;
+                int64_t gy = ty0 + r;
+                gy = gy < 0 ? 0 : gy > A.nrows - 1 ? A.nrows - 1 : gy;
+                const int16_t *src = A.z + gy * A.ld;
+#pragma unroll
+                for (int cc = 0; cc < 4; cc++) {
+                    const int c = lane + 64 * cc;
+                    int64_t gx = tx0 + c;
+                    gx = gx < 0 ? 0 : gx > A.ncols - 1 ? A.ncols - 1 : gx;
+                    v[u][cc] = (r < th && c < tw) ? src[gx] : (int16_t)0;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int r = r0 + u * kFwdWaves;
+#pragma unroll
+                for (int cc = 0; cc < 4; cc++) {
+                    const int c = lane + 64 * cc;
+                    if (r < th && c < tw)
+                        tile[r * tw + c] = v[u][cc];
+                }
+            }
         }
         __syncthreads();
         nloc = A.BL * A.BL;
