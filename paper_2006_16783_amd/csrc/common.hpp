@@ -48,6 +48,45 @@ int kernel_max_dynamic_lds(const void *kernel);
 
 inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Wavefront reductions on DPP lane moves (row shifts by 1, 2, 4, 8, then the
+// row broadcasts of lanes 15 and 31): lane 63 ends with the result, which is
+// returned to every lane.  Lanes a move leaves without a source, and rows the
+// row mask excludes, read the identity 0.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ uint32_t dpp_move(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kCtrl, kRowMask, 0xF, false);
+}
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ uint64_t dpp_move64(uint64_t v)
+{
+    return ((uint64_t)dpp_move<kCtrl, kRowMask>((uint32_t)(v >> 32)) << 32) |
+           dpp_move<kCtrl, kRowMask>((uint32_t)v);
+}
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v)
+{
+    uint64_t w;
+    w = dpp_move64<0x111, 0xF>(v); v = w > v ? w : v;
+    w = dpp_move64<0x112, 0xF>(v); v = w > v ? w : v;
+    w = dpp_move64<0x114, 0xF>(v); v = w > v ? w : v;
+    w = dpp_move64<0x118, 0xF>(v); v = w > v ? w : v;
+    w = dpp_move64<0x142, 0xA>(v); v = w > v ? w : v;
+    w = dpp_move64<0x143, 0xC>(v); v = w > v ? w : v;
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63) << 32) |
+           (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+}
+// sum of 32-bit values (the total must fit 32 bits)
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
+{
+    v += dpp_move<0x111, 0xF>(v);
+    v += dpp_move<0x112, 0xF>(v);
+    v += dpp_move<0x114, 0xF>(v);
+    v += dpp_move<0x118, 0xF>(v);
+    v += dpp_move<0x142, 0xA>(v);
+    v += dpp_move<0x143, 0xC>(v);
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
 constexpr int32_t kMaxRoi = 16383;
 constexpr int32_t kMaxHeight = 32767;
 

@@ -33,16 +33,6 @@ __device__ __forceinline__ uint32_t ord_f32(float f)
     return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
 }
 
-__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v)
-{
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-        uint64_t w = __shfl_xor(v, o, 64);
-        v = w > v ? w : v;
-    }
-    return v;
-}
-
 // kVec (u8 keys only): key rows and terrain rows start 16-byte aligned, and
 // every lane streams 16 posts per step with three 16-byte loads.
 template <bool kF32, bool kVec>

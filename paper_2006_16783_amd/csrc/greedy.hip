@@ -35,23 +35,8 @@ constexpr int kGreedyWaves = kGreedyThreads / 64;
 constexpr int kGreedyBlock = 1024;   // candidates per bmax entry
 constexpr int kGreedyMaxBlocks = 16384;
 
-__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v)
-{
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-        uint64_t w = __shfl_xor(v, o, 64);
-        v = w > v ? w : v;
-    }
-    return v;
-}
-
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
-{
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1)
-        v += __shfl_xor(v, o, 64);
-    return v;
-}
+// popcount totals of a window: at most (2*16383+1)^2 < 2^31 bits
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) { return wave_sum_u32((uint32_t)v); }
 
 struct Win {
     int64_t ylo, w0;
@@ -178,7 +163,7 @@ __device__ __forceinline__ void wave_block_max(const uint64_t *key, const int32_
     }
     best = wave_max_u64(v);
     const uint64_t owner = __ballot(v == best && best != 0);
-    bfr = __shfl(f, owner ? __ffsll((long long)owner) - 1 : 0, 64);
+    bfr = __builtin_amdgcn_readlane(f, owner ? __ffsll((long long)owner) - 1 : 0);
 }
 
 __global__ __launch_bounds__(kGreedyThreads) void greedy_run(
@@ -247,7 +232,7 @@ __global__ __launch_bounds__(kGreedyThreads) void greedy_run(
         const uint64_t wmax = wave_max_u64(m1);
         const uint64_t owner = __ballot(m1 == wmax && wmax != 0);
         const int ol = owner ? __ffsll((long long)owner) - 1 : 0;
-        const int wb = __shfl(b1, ol, 64);
+        const int wb = __builtin_amdgcn_readlane(b1, ol);
         // the wavefront's second: the owner's own second or another lane's first
         const uint64_t wsec = wave_max_u64(lane == ol ? m2 : m1);
         if (lane == 0) {

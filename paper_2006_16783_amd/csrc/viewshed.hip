@@ -43,14 +43,6 @@ __device__ __forceinline__ int wave_max_i32(int v)
     return v;
 }
 
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
-{
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1)
-        v += __shfl_xor(v, o, 64);
-    return v;
-}
-
 // Geometry of one quadrant in its local frame (u along the quadrant's first
 // axis, v along the second; u > 0, v >= 0).  Global offsets of local (u, v):
 //   Q0: ( u,  v)   Q1: (-v,  u)   Q2: (-u, -v)   Q3: ( v, -u)
