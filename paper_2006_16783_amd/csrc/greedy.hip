@@ -178,15 +178,17 @@ __global__ __launch_bounds__(kGreedyThreads) void greedy_run(
     const int64_t W = (ncols + 63) >> 6;
     const int nblocks = (int)((n + kGreedyBlock - 1) / kGreedyBlock);
     int32_t *bfr = reinterpret_cast<int32_t *>(bmax + nblocks);
+    // per-wavefront partials: s_t* for the top selection, s_a/s_b for the
+    // pass's reduction (separate, so neither needs a barrier before reuse)
+    __shared__ uint64_t s_t1[kGreedyWaves], s_t2[kGreedyWaves];
     __shared__ uint64_t s_a[kGreedyWaves], s_b[kGreedyWaves];
-    __shared__ int32_t s_f;
 
     // workgroup sum of a and max of b in one exchange (results in every
-    // thread)
+    // thread); s_a/s_b were last read before the previous round's final
+    // barrier
     auto wg_sum_max = [&](uint64_t a, uint64_t b, uint64_t &sa, uint64_t &mb) {
         a = wave_sum_u64(a);
         b = wave_max_u64(b);
-        __syncthreads();
         if (lane == 0) {
             s_a[wave] = a;
             s_b[wave] = b;
@@ -236,15 +238,15 @@ __global__ __launch_bounds__(kGreedyThreads) void greedy_run(
         // the wavefront's second: the owner's own second or another lane's first
         const uint64_t wsec = wave_max_u64(lane == ol ? m2 : m1);
         if (lane == 0) {
-            s_a[wave] = wmax;
-            s_b[wave] = wsec;
+            s_t1[wave] = wmax;
+            s_t2[wave] = wsec;
         }
         __syncthreads();
         uint64_t top = 0, second = 0;
         int rank = 0;  // wavefronts holding a larger top than this one
         int tw = 0;
         for (int w2 = 0; w2 < kGreedyWaves; w2++) {
-            const uint64_t v = s_a[w2];
+            const uint64_t v = s_t1[w2];
             if (v > top) {
                 top = v;
                 tw = w2;
@@ -252,7 +254,7 @@ __global__ __launch_bounds__(kGreedyThreads) void greedy_run(
             rank += v > wmax;
         }
         for (int w2 = 0; w2 < kGreedyWaves; w2++) {
-            const uint64_t v = w2 == tw ? s_b[w2] : s_a[w2];
+            const uint64_t v = w2 == tw ? s_t2[w2] : s_t1[w2];
             second = v > second ? v : second;
         }
         const int64_t i = (int64_t)(0xFFFFFFFFull - (top & 0xFFFFFFFFull));
@@ -260,8 +262,8 @@ __global__ __launch_bounds__(kGreedyThreads) void greedy_run(
         if (top == 0 || i >= n)
             break;  // unreachable with n >= 1
         const int bi = (int)(i / kGreedyBlock);
+        // (bmax/bfr change only after the pass's reduction barrier)
         const int32_t fr = bfr[bi];
-        __syncthreads();  // every thread has read s_a, s_b and bfr
         if (fr == t || pass == 0) {
             // Re-evaluate the top if it is stale (the whole workgroup, one
             // window word per thread), and take it if it is fresh or stays
@@ -308,10 +310,12 @@ __global__ __launch_bounds__(kGreedyThreads) void greedy_run(
             const uint64_t ki = take ? (0xFFFFFFFFull - (uint64_t)i) : nk;
             const int32_t fi = take ? t + 1 : t;
             const uint64_t bm2 = ki > bo ? ki : bo;
-            if (bm2 == bo && kj_ex == bo && bo != 0)
-                s_f = fj;  // the block's new maximum is another candidate's
-            if (tid == 0 && bm2 == ki)
-                s_f = fi;
+            // the holder of the block's new maximum records it (another
+            // candidate's, or i's own new key)
+            if ((bm2 == bo && kj_ex == bo && bo != 0) || (bm2 == ki && j == i)) {
+                bmax[bi] = bm2;
+                bfr[bi] = j == i ? fi : fj;
+            }
             if (take) {
                 for (int e = tid; e < words; e += kGreedyThreads) {
                     const int row = e / w.nw, c = e - row * w.nw;
@@ -319,16 +323,13 @@ __global__ __launch_bounds__(kGreedyThreads) void greedy_run(
                     *ce = e == tid ? (c0 | v0) : (*ce | v[e]);
                 }
             }
-            __syncthreads();
-            if (tid == 0) {
+            if (j == i) {
                 key[i] = ki;
                 fresh[i] = fi;
-                bmax[bi] = bm2;
-                bfr[bi] = s_f;
-                if (take) {
-                    selected[t] = i;
-                    gains[t] = (int64_t)gain;
-                }
+            }
+            if (tid == 0 && take) {
+                selected[t] = i;
+                gains[t] = (int64_t)gain;
             }
             if (take) {
                 covered += (int64_t)gain;
