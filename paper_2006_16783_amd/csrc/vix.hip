@@ -201,7 +201,8 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
         int bt = 0;
         if (lane == 0)
             bt = atomicAdd(&s_batch, 1);
-        return __shfl(bt, 0, 64);
+        // wave-uniform: keeps the queue bookkeeping in scalar registers
+        return __builtin_amdgcn_readfirstlane(__shfl(bt, 0, 64));
     };
     // this lane's post of batch bt
     auto post_of = [&](int bt, int &py, int &px) {
@@ -337,131 +338,143 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
     // step (scaled by n); k: steps left; pl: count slot
     int n = 0, mn = 0, off = 0, smaj = 0, smin = 0, rhs = 0, dz = 0, k = 0, pl = 0;
     uint32_t eu = 0;
+    // idle lanes take the next tests of the queue, in order
+    auto take = [&]() {
+        const bool idle = !active;
+        const uint64_t m = __ballot(idle);
+        const int idx = cursor + __popcll(m & lt_mask);
+        const int src = idx & 63;
+        const uint32_t v0 = lane_read(src, e[0]), v1 = lane_read(src, e[1]);
+        const int spo = (int)lane_read(src, (uint32_t)po);
+        const int sE = (int)lane_read(src, (uint32_t)Epost);
+        const uint32_t ent = (idx >> 6) == (cursor >> 6) ? v0 : v1;
+        if (idle && idx < total && ent != kSkip) {
+            const int dx = (int)((ent >> 13) & 0x1FFF) - 4096;
+            const int dy = (int)(ent & 0x1FFF) - 4096;
+            const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
+            const bool xmaj = adx >= ady;
+            const int cidx = (buf << 6) | src;
+            n = xmaj ? adx : ady;
+            if (n <= 1) {
+                add_visible(cidx);  // adjacent: always visible
+            } else {
+                const int sx = dx < 0 ? -1 : 1, sy = dy < 0 ? -rs : rs;
+                const int es = kLds ? 2 : 1;  // offset units per post
+                mn = xmaj ? ady : adx;
+                smaj = (xmaj ? sx : sy) * es;
+                smin = (xmaj ? sy : sx) * es;
+                const int tgt = spo + (kLds ? mul_i24(dy, rs) : dy * rs) + dx;
+                const int Zt = (int)zb[tgt] + h_r;
+                off = kLds ? tb + spo * 2 : spo;
+                rhs = sE * n;
+                dz = Zt - sE;
+                eu = (uint32_t)-n;
+                k = n - 1;  // steps left
+                pl = cidx;
+                active = true;
+            }
+        }
+        const int c1 = cursor + __popcll(m);
+        if ((c1 >> 6) != (cursor >> 6)) {
+#pragma unroll
+            for (int j = 0; j + 1 < kVixChunk; j++)
+                e[j] = e[j + 1];
+        }
+        cursor = c1;
+    };
+
+    // kSPI steps of every active test: positions and reads first, then the
+    // comparisons, so a test waits for memory once per block
+    auto step_block = [&]() {
+        if (!active)
+            return;
+        int sa[kSPI], sb[kSPI], se[kSPI];
+#pragma unroll
+        for (int sp = 0; sp < kSPI; sp++) {
+            uint32_t e1;
+            const bool wrap = __builtin_add_overflow(eu, (uint32_t)mn, &e1);
+            eu = wrap ? e1 - (uint32_t)n : e1;
+            off += smaj + (wrap ? smin : 0);
+            se[sp] = (int)eu;
+            if (kLds) {
+                // past the end of the LOS these reads land in the halo
+                sa[sp] = lds_read_i16(off);
+                sb[sp] = lds_read_i16(off + smin);
+            } else {
+                sa[sp] = 0;
+                sb[sp] = 0;
+                if (sp < k) {
+                    sa[sp] = zb[off];
+                    sb[sp] = zb[off + smin];  // in the observer-target box
+                }
+            }
+        }
+        // terrain above the segment: z0*n + (z1-z0)*r = z1*n + (z1-z0)*e
+        bool blocked = false;
+        int first = kSPI;
+#pragma unroll
+        for (int sp = 0; sp < kSPI; sp++) {
+            rhs += dz;
+            const int S = mad_i24(sb[sp] - sa[sp], se[sp], mul_i24(sb[sp], n));
+            const bool bs = sp < k && S > rhs;
+            blocked |= bs;
+            if (kCount && bs && first == kSPI)
+                first = sp;
+        }
+        if (kCount)
+            steps += blocked ? first + 1 : (k < kSPI ? k : kSPI);
+        k -= kSPI;
+        if (blocked || k <= 0) {
+            if (!blocked)
+                add_visible(pl);
+            active = false;
+        }
+    };
+
     for (;;) {
-        if (cursor >= total) {
-            // queue drained: next chunk of this batch, or the next batch once
-            // the count buffer it takes has no test running
-            if (j0 + kc < K) {
-                j0 += kc;
-                generate();
-            } else if (more) {
-                const int nb = (buf + 1) & (kVixBufs - 1);
-                bool can = true;
-                if (pending & (1u << nb)) {
-                    if (__any(active && (pl >> 6) == nb)) {
-                        can = false;
-                    } else {
-                        retire(nb, (int)((bt_of >> (16 * nb)) & 0xFFFF));
-                        pending &= ~(1u << nb);
-                    }
-                }
-                if (can) {
-                    const int bt = claim();
-                    if (bt >= nbatch) {
-                        more = false;
-                    } else {
-                        pending |= 1u << buf;
-                        bt_of = (bt_of & ~(0xFFFFull << (16 * buf))) |
-                                ((uint64_t)cur_bt << (16 * buf));
-                        buf = nb;
-                        cur_bt = bt;
-                        setup(bt);
-                        generate();
-                    }
-                }
-            }
-            if (cursor >= total && !more && !__any(active))
-                break;
+        // the hot loop: the queue holds tests
+        while (cursor < total) {
+            take();
+            step_block();
         }
-        if (cursor < total) {
-            // idle lanes take the next tests of the queue, in order
-            const bool idle = !active;
-            const uint64_t m = __ballot(idle);
-            const int idx = cursor + __popcll(m & lt_mask);
-            const int src = idx & 63;
-            const uint32_t v0 = lane_read(src, e[0]), v1 = lane_read(src, e[1]);
-            const int spo = (int)lane_read(src, (uint32_t)po);
-            const int sE = (int)lane_read(src, (uint32_t)Epost);
-            const uint32_t ent = (idx >> 6) == (cursor >> 6) ? v0 : v1;
-            if (idle && idx < total && ent != kSkip) {
-                const int dx = (int)((ent >> 13) & 0x1FFF) - 4096;
-                const int dy = (int)(ent & 0x1FFF) - 4096;
-                const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
-                const bool xmaj = adx >= ady;
-                const int cidx = (buf << 6) | src;
-                n = xmaj ? adx : ady;
-                if (n <= 1) {
-                    add_visible(cidx);  // adjacent: always visible
+        // queue drained: next chunk of this batch, or the next batch once
+        // the count buffer it takes has no test running
+        if (j0 + kc < K) {
+            j0 += kc;
+            generate();
+            continue;
+        }
+        if (more) {
+            const int nb = (buf + 1) & (kVixBufs - 1);
+            bool can = true;
+            if (pending & (1u << nb)) {
+                if (__any(active && (pl >> 6) == nb)) {
+                    can = false;
                 } else {
-                    const int sx = dx < 0 ? -1 : 1, sy = dy < 0 ? -rs : rs;
-                    const int es = kLds ? 2 : 1;  // offset units per post
-                    mn = xmaj ? ady : adx;
-                    smaj = (xmaj ? sx : sy) * es;
-                    smin = (xmaj ? sy : sx) * es;
-                    const int tgt = spo + (kLds ? mul_i24(dy, rs) : dy * rs) + dx;
-                    const int Zt = (int)zb[tgt] + h_r;
-                    off = kLds ? tb + spo * 2 : spo;
-                    rhs = sE * n;
-                    dz = Zt - sE;
-                    eu = (uint32_t)-n;
-                    k = n - 1;  // steps left
-                    pl = cidx;
-                    active = true;
+                    retire(nb, (int)((bt_of >> (16 * nb)) & 0xFFFF));
+                    pending &= ~(1u << nb);
                 }
             }
-            const int c1 = cursor + __popcll(m);
-            if ((c1 >> 6) != (cursor >> 6)) {
-#pragma unroll
-                for (int j = 0; j + 1 < kVixChunk; j++)
-                    e[j] = e[j + 1];
-            }
-            cursor = c1;
-        }
-        if (active) {
-            // kSPI steps at once: positions and reads first, then the
-            // comparisons, so the step loop waits for memory once per block
-            int sa[kSPI], sb[kSPI], se[kSPI];
-#pragma unroll
-            for (int sp = 0; sp < kSPI; sp++) {
-                uint32_t e1;
-                const bool wrap = __builtin_add_overflow(eu, (uint32_t)mn, &e1);
-                eu = wrap ? e1 - (uint32_t)n : e1;
-                off += smaj + (wrap ? smin : 0);
-                se[sp] = (int)eu;
-                if (kLds) {
-                    // past the end of the LOS these reads land in the halo
-                    sa[sp] = lds_read_i16(off);
-                    sb[sp] = lds_read_i16(off + smin);
+            if (can) {
+                const int bt = claim();
+                if (bt >= nbatch) {
+                    more = false;
                 } else {
-                    sa[sp] = 0;
-                    sb[sp] = 0;
-                    if (sp < k) {
-                        sa[sp] = zb[off];
-                        sb[sp] = zb[off + smin];  // in the observer-target box
-                    }
+                    pending |= 1u << buf;
+                    bt_of = (bt_of & ~(0xFFFFull << (16 * buf))) |
+                            ((uint64_t)cur_bt << (16 * buf));
+                    buf = nb;
+                    cur_bt = bt;
+                    setup(bt);
+                    generate();
+                    continue;
                 }
             }
-            // terrain above the segment: z0*n + (z1-z0)*r = z1*n + (z1-z0)*e
-            bool blocked = false;
-            int first = kSPI;
-#pragma unroll
-            for (int sp = 0; sp < kSPI; sp++) {
-                rhs += dz;
-                const int S = mad_i24(sb[sp] - sa[sp], se[sp], mul_i24(sb[sp], n));
-                const bool bs = sp < k && S > rhs;
-                blocked |= bs;
-                if (kCount && bs && first == kSPI)
-                    first = sp;
-            }
-            if (kCount)
-                steps += blocked ? first + 1 : (k < kSPI ? k : kSPI);
-            k -= kSPI;
-            if (blocked || k <= 0) {
-                if (!blocked)
-                    add_visible(pl);
-                active = false;
-            }
         }
+        if (!more && !__any(active))
+            break;
+        // no new tests yet (or none left): advance the running ones
+        step_block();
     }
     retire(buf, cur_bt);
     for (int bf = 0; bf < kVixBufs; bf++)
