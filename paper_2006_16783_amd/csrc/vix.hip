@@ -220,8 +220,8 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
     int bxo = 0, byo = 0;         // clipped box corner relative to the post
     uint32_t wx = 0, wy = 0;      // clipped box extent
     uint32_t tx = 0, ty = 0;      // Lemire thresholds 2^16 mod wx, wy
-    uint32_t blk_next = 0, w0 = 0, w1 = 0, w2 = 0, w3 = 0;
-    int nbuf = 0;
+    uint32_t blk_next = 0;  // next Philox block of the post's stream
+    int nbuf = 0;           // words of block blk_next-1 not yet used
     // earlier batches whose tests may still run: bit b of `pending` says
     // that count buffer b holds batch (bt_of >> 16b) & 0xffff
     uint32_t pending = 0;
@@ -260,41 +260,50 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
             e[j] = kSkip;
         int made = 0, att = 0;
         const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-        while (__any(made < need)) {
-            const bool want = made < need && nbuf == 0;
-            if (__any(want)) {
-                uint32_t o[4];
-                philox4x32_10((uint32_t)t, blk_next, (uint32_t)(t >> 32), 0, k0, k1, o);
-                if (want) {
-                    w0 = o[0]; w1 = o[1]; w2 = o[2]; w3 = o[3];
-                    blk_next++;
-                    nbuf = 4;
-                }
-            }
+        // one proposal: 16-bit halves scaled to the box with Lemire's
+        // rejection, then the disk test; an accepted draw (or a failed one
+        // after kVixMaxAttempts rejections) is appended to the lane's queue.
+        // Branch-free, so that the queue shifts in place.
+        auto propose = [&](uint32_t u, bool live) {
+            const uint32_t mx = __umul24(u & 0xFFFFu, wx), my = __umul24(u >> 16, wy);
+            const int dx = bxo + (int)(mx >> 16);
+            const int dy = byo + (int)(my >> 16);
+            const bool ok = (mx & 0xFFFFu) >= tx && (my & 0xFFFFu) >= ty &&
+                            (dx | dy) != 0 && __mul24(dx, dx) + __mul24(dy, dy) <= R2;
+            const int att1 = att + 1;
+            const bool acc = live && (ok || att1 == kVixMaxAttempts);
+            att = acc ? 0 : (live ? att1 : att);
+#pragma unroll
+            for (int j = 0; j + 1 < kVixChunk; j++)
+                e[j] = acc ? e[j + 1] : e[j];
+            e[kVixChunk - 1] = acc ? (ok ? pack_test(dx, dy) : kSkip) : e[kVixChunk - 1];
+            made += acc ? 1 : 0;
+            if (kCount && acc && ok)
+                tests++;
+        };
+        // words left in block blk_next-1 by the previous chunk of the post
+        if (__any(made < need && nbuf > 0)) {
+            uint32_t o[4];
+            philox4x32_10((uint32_t)t, blk_next - 1, (uint32_t)(t >> 32), 0, k0, k1, o);
+            const int nb0 = nbuf;
 #pragma unroll
             for (int i = 0; i < 4; i++) {
-                if (made < need && nbuf > 0) {
-                    const uint32_t u = nbuf == 4 ? w0 : nbuf == 3 ? w1 : nbuf == 2 ? w2 : w3;
-                    nbuf--;
-                    att++;
-                    // 16-bit halves scaled to the box, Lemire's rejection
-                    const uint32_t mx = __umul24(u & 0xFFFFu, wx), my = __umul24(u >> 16, wy);
-                    const int dx = bxo + (int)(mx >> 16);
-                    const int dy = byo + (int)(my >> 16);
-                    const bool ok = (mx & 0xFFFFu) >= tx && (my & 0xFFFFu) >= ty &&
-                                    (dx | dy) != 0 && __mul24(dx, dx) + __mul24(dy, dy) <= R2;
-                    if (ok || att == kVixMaxAttempts) {
-                        // append: shift the lane's queue down one row
+                const bool live = made < need && i >= 4 - nb0;
+                nbuf = live ? 3 - i : nbuf;
+                propose(o[i], live);
+            }
+        }
+        // a new block per round for every lane that still needs draws
+        while (__any(made < need)) {
+            uint32_t o[4];
+            philox4x32_10((uint32_t)t, blk_next, (uint32_t)(t >> 32), 0, k0, k1, o);
+            const bool want = made < need;
+            blk_next += want ? 1 : 0;
 #pragma unroll
-                        for (int j = 0; j + 1 < kVixChunk; j++)
-                            e[j] = e[j + 1];
-                        e[kVixChunk - 1] = ok ? pack_test(dx, dy) : kSkip;
-                        made++;
-                        att = 0;
-                        if (kCount && ok)
-                            tests++;
-                    }
-                }
+            for (int i = 0; i < 4; i++) {
+                const bool live = made < need;
+                nbuf = live ? 3 - i : nbuf;
+                propose(o[i], live);
             }
         }
         // rows 0..kc-1 to e[0..kc-1]
@@ -366,7 +375,7 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
                 const int tgt = spo + (kLds ? mul_i24(dy, rs) : dy * rs) + dx;
                 const int Zt = (int)zb[tgt] + h_r;
                 off = kLds ? tb + spo * 2 : spo;
-                rhs = sE * n;
+                rhs = mul_i24(sE, n);  // |sE| < 2^17, n < 2^14
                 dz = Zt - sE;
                 eu = (uint32_t)-n;
                 k = n - 1;  // steps left
@@ -439,12 +448,11 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
         }
         // queue drained: next chunk of this batch, or the next batch once
         // the count buffer it takes has no test running
+        bool gen = false;
         if (j0 + kc < K) {
             j0 += kc;
-            generate();
-            continue;
-        }
-        if (more) {
+            gen = true;
+        } else if (more) {
             const int nb = (buf + 1) & (kVixBufs - 1);
             bool can = true;
             if (pending & (1u << nb)) {
@@ -466,10 +474,13 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
                     buf = nb;
                     cur_bt = bt;
                     setup(bt);
-                    generate();
-                    continue;
+                    gen = true;
                 }
             }
+        }
+        if (gen) {
+            generate();
+            continue;
         }
         if (!more && !__any(active))
             break;
