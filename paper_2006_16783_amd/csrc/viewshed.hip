@@ -416,22 +416,49 @@ __global__ void viewshed_kernel(const int16_t *__restrict__ z, int64_t nrows, in
                 }
                 int zmin = 32767, zmax = -32768;
                 const int bw = (int)(gx1 - gx0 + 1), bh = (int)(gy1 - gy0 + 1);
-                for (int row = wave; row < bh; row += nwaves) {
-                    const int16_t *src = z + (gy0 + row) * ld + gx0;
-                    const int gy = (int)(gy0 + row - y);
-                    for (int col = lane; col < bw; col += 64) {
-                        int v = src[col];
-                        int gx = (int)(gx0 + col - x);
-                        int lu, lv;
-                        switch (qd) {
-                        case 0: lu = gx;  lv = gy;  break;
-                        case 1: lu = gy;  lv = -gx; break;
-                        case 2: lu = -gx; lv = -gy; break;
-                        default: lu = -gy; lv = gx; break;
-                        }
-                        zq[lv * zp + lu] = (int16_t)v;
-                        zmin = min(zmin, v);
-                        zmax = max(zmax, v);
+                // local offset of global (gy0 + row, gx0 + col) under the
+                // quadrant's rotation: base + row * RS + col * CS
+                const int dgx = (int)(gx0 - x), dgy = (int)(gy0 - y);
+                int RS, CS, base;
+                switch (qd) {
+                case 0: RS = zp;  CS = 1;   base = dgy * zp + dgx; break;  // (u, v) = ( gx,  gy)
+                case 1: RS = 1;   CS = -zp; base = dgy - dgx * zp; break;  // (u, v) = ( gy, -gx)
+                case 2: RS = -zp; CS = -1;  base = -dgy * zp - dgx; break; // (u, v) = (-gx, -gy)
+                default: RS = -1; CS = zp;  base = dgx * zp - dgy; break;  // (u, v) = (-gy,  gx)
+                }
+                // four rows per wavefront and two 64-post chunks per row in
+                // flight before the LDS writes
+                for (int row = wave; row < bh; row += 4 * nwaves) {
+                    const int16_t *sp[4];
+                    int rb[4];
+                    bool rv[4];
+#pragma unroll
+                    for (int u = 0; u < 4; u++) {
+                        const int r = row + u * nwaves;
+                        rv[u] = r < bh;
+                        sp[u] = z + (gy0 + (rv[u] ? r : 0)) * ld + gx0;
+                        rb[u] = base + r * RS;
+                    }
+                    for (int c0 = lane; c0 < bw; c0 += 128) {
+                        int v[4][2];
+#pragma unroll
+                        for (int u = 0; u < 4; u++)
+#pragma unroll
+                            for (int h = 0; h < 2; h++) {
+                                const int col = c0 + 64 * h;
+                                v[u][h] = rv[u] && col < bw ? (int)sp[u][col] : 0;
+                            }
+#pragma unroll
+                        for (int u = 0; u < 4; u++)
+#pragma unroll
+                            for (int h = 0; h < 2; h++) {
+                                const int col = c0 + 64 * h;
+                                if (rv[u] && col < bw) {
+                                    zq[rb[u] + col * CS] = (int16_t)v[u][h];
+                                    zmin = min(zmin, v[u][h]);
+                                    zmax = max(zmax, v[u][h]);
+                                }
+                            }
                     }
                 }
                 zmin = wave_min_i32(zmin);

@@ -226,10 +226,15 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
     // that count buffer b holds batch (bt_of >> 16b) & 0xffff
     uint32_t pending = 0;
     uint64_t bt_of = 0;
-    // queue of the current chunk: row j of the queue is draw j0+j of every
-    // lane's post; e[0] holds row (cursor >> 6) of this lane's post
+    // queue of the current chunk: e[j] holds draw j0+j of this lane's post
+    // (row j of the wavefront's queue)
     uint32_t e[kVixChunk];
     int j0 = 0, kc = 0, cursor = 0, total = 0;
+    // row r of the queue (r wave-uniform; kSkip past the end)
+    auto e_row = [&](int r) {
+        const uint32_t v = e[r < kVixChunk ? r : kVixChunk - 1];  // indexed register read
+        return r < kVixChunk ? v : kSkip;
+    };
 
     auto setup = [&](int bt) {
         int py, px;
@@ -353,7 +358,8 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
         const uint64_t m = __ballot(idle);
         const int idx = cursor + __popcll(m & lt_mask);
         const int src = idx & 63;
-        const uint32_t v0 = lane_read(src, e[0]), v1 = lane_read(src, e[1]);
+        const int row = cursor >> 6;
+        const uint32_t v0 = lane_read(src, e_row(row)), v1 = lane_read(src, e_row(row + 1));
         const int spo = (int)lane_read(src, (uint32_t)po);
         const int sE = (int)lane_read(src, (uint32_t)Epost);
         const uint32_t ent = (idx >> 6) == (cursor >> 6) ? v0 : v1;
@@ -384,11 +390,6 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
             }
         }
         const int c1 = cursor + __popcll(m);
-        if ((c1 >> 6) != (cursor >> 6)) {
-#pragma unroll
-            for (int j = 0; j + 1 < kVixChunk; j++)
-                e[j] = e[j + 1];
-        }
         cursor = c1;
     };
 
