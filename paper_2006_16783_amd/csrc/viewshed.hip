@@ -198,14 +198,15 @@ __device__ __forceinline__ int lds_read_i16(int addr)
 //    disk (k^2 + (q+1)^2 <= R^2), so those steps skip the disk test;
 //  * the receiver's line is tested as T*J + h_r*n*J >= hN*k with one
 //    multiply-add (h_r*n < 2^23 in narrow mode);
-//  * post offsets are LDS byte addresses (zq_addr: the observer's post).
-__device__ __forceinline__ void sweep_lds_narrow(int zq_addr, int zp, uint32_t *bm, int P0,
-                                                 int bu, int bv, int du, int dv, int R2, int E,
-                                                 int h_r)
+//  * post offsets are LDS byte addresses (zq_addr: the observer's post;
+//    zs_u, zs_v: the byte steps of local u and v in the staged quadrant).
+__device__ __forceinline__ void sweep_lds_narrow(int zq_addr, int zs_u, int zs_v, uint32_t *bm,
+                                                 int P0, int bu, int bv, int du, int dv, int R2,
+                                                 int E, int h_r)
 {
     const bool umaj = du >= dv;
     const int n = umaj ? du : dv, mn = umaj ? dv : du;
-    const int zs_maj = umaj ? 2 : 2 * zp, zs_min = umaj ? 2 * zp : 2;
+    const int zs_maj = umaj ? zs_u : zs_v, zs_min = umaj ? zs_v : zs_u;
     const int bs_maj = umaj ? bu : bv, bs_min = umaj ? bv : bu;
     const int nEn = -E * n;
     const int hrn = h_r * n;
@@ -314,16 +315,19 @@ __host__ __device__ __forceinline__ int bm_bytes(int rmax)
 {
     return (2 * rmax + 1) * bm_pitch_dw(rmax) * 4;
 }
-__host__ __device__ __forceinline__ int zq_pitch(int rmax)
+// A staged quadrant box (at most rmax+1 rows of rmax+1 posts) keeps the
+// terrain's orientation; its rows start at an even terrain column, so a row
+// spans at most rmax+2 posts, and an odd dword pitch puts a column's posts in
+// distinct banks.  A ray whose line meets a post exactly still reads the next
+// post along the minor axis (with weight zero), which can lie one row past the
+// box: one spare row keeps that read inside the allocation.
+__host__ __device__ __forceinline__ int zq_pitch_dw(int rmax)
 {
-    int p = (rmax + 2 + 1) & ~1;  // even element count ...
-    if (((p >> 1) & 1) == 0)      // ... whose dword count is odd
-        p += 2;
-    return p;
+    return ((rmax + 3) >> 1) | 1;
 }
 __host__ __device__ __forceinline__ int zq_bytes(int rmax)
 {
-    return rmax > 0 ? (rmax + 2) * zq_pitch(rmax) * 2 : 0;
+    return rmax > 0 ? (rmax + 2) * zq_pitch_dw(rmax) * 4 : 0;
 }
 
 __global__ void viewshed_queue_reset(uint32_t *queue) { queue[0] = 0; }
@@ -344,7 +348,7 @@ __global__ void viewshed_kernel(const int16_t *__restrict__ z, int64_t nrows, in
                                 const int32_t *__restrict__ order, int sink,
                                 uint64_t *__restrict__ bitmaps, uint32_t *__restrict__ visible,
                                 uint32_t *__restrict__ cells, uint32_t *queue, int rmax,
-                                int stage_rmax)
+                                int stage_rmax, int dma)
 {
     extern __shared__ uint32_t lds[];
     __shared__ int64_t s_task;
@@ -354,8 +358,8 @@ __global__ void viewshed_kernel(const int16_t *__restrict__ z, int64_t nrows, in
     const int wave = tid >> 6, lane = tid & 63, nwaves = nthreads >> 6;
     uint32_t *bm = lds;
     int16_t *zq = reinterpret_cast<int16_t *>(lds + bm_bytes(rmax) / 4);
-    const int zp = zq_pitch(stage_rmax);
-    // LDS byte address of the staged quadrant's origin (the observer's post)
+    const int zpd = zq_pitch_dw(stage_rmax);  // staged row pitch (dwords)
+    // LDS byte address of the staged box
     const int zq_addr =
         (int)(uint32_t)(uintptr_t)(const __attribute__((address_space(3))) int16_t *)zq;
     const int BPdw = bm_pitch_dw(rmax);
@@ -414,51 +418,73 @@ __global__ void viewshed_kernel(const int16_t *__restrict__ z, int64_t nrows, in
                 case 2: gx0 = x - Q.eu;  gx1 = x;        gy0 = y - Q.ev;  gy1 = y;        break;
                 default: gx0 = x;        gx1 = x + Q.ev; gy0 = y - Q.eu;  gy1 = y;        break;
                 }
+                // stage the quadrant's box in the terrain's orientation, its
+                // rows from the even column gxe
                 int zmin = 32767, zmax = -32768;
                 const int bw = (int)(gx1 - gx0 + 1), bh = (int)(gy1 - gy0 + 1);
-                // local offset of global (gy0 + row, gx0 + col) under the
-                // quadrant's rotation: base + row * RS + col * CS
-                const int dgx = (int)(gx0 - x), dgy = (int)(gy0 - y);
-                int RS, CS, base;
-                switch (qd) {
-                case 0: RS = zp;  CS = 1;   base = dgy * zp + dgx; break;  // (u, v) = ( gx,  gy)
-                case 1: RS = 1;   CS = -zp; base = dgy - dgx * zp; break;  // (u, v) = ( gy, -gx)
-                case 2: RS = -zp; CS = -1;  base = -dgy * zp - dgx; break; // (u, v) = (-gx, -gy)
-                default: RS = -1; CS = zp;  base = dgx * zp - dgy; break;  // (u, v) = (-gy,  gx)
-                }
-                // four rows per wavefront and two 64-post chunks per row in
-                // flight before the LDS writes
-                for (int row = wave; row < bh; row += 4 * nwaves) {
-                    const int16_t *sp[4];
-                    int rb[4];
-                    bool rv[4];
-#pragma unroll
-                    for (int u = 0; u < 4; u++) {
-                        const int r = row + u * nwaves;
-                        rv[u] = r < bh;
-                        sp[u] = z + (gy0 + (rv[u] ? r : 0)) * ld + gx0;
-                        rb[u] = base + r * RS;
+                const int64_t gxe = gx0 & ~(int64_t)1;
+                const int c0 = (int)(gx0 - gxe);
+                if (dma) {
+                    // each wavefront streams its rows straight into LDS
+                    // (global_load_lds: lane i writes the dword at the LDS base
+                    // + 4i), all of them in flight before one wait.  With ld and
+                    // ncols even every dword lies inside its row.
+                    const int ndw = (int)((gx1 - gxe) >> 1) + 1;
+                    uint32_t *zd = reinterpret_cast<uint32_t *>(zq);
+                    for (int r = wave; r < bh; r += nwaves) {
+                        const uint32_t *srow =
+                            reinterpret_cast<const uint32_t *>(z + (gy0 + r) * ld + gxe);
+                        for (int k0 = 0; k0 < ndw; k0 += 64)
+                            if (k0 + lane < ndw)
+                                __builtin_amdgcn_global_load_lds(srow + k0 + lane,
+                                                                 zd + r * zpd + k0, 4, 0, 0);
                     }
-                    for (int c0 = lane; c0 < bw; c0 += 128) {
-                        int v[4][2];
+                    __builtin_amdgcn_s_waitcnt(0);
+                    __syncthreads();
+                    // elevation range (a post left of gx0 or right of gx1 is
+                    // terrain too: it can only widen the range)
+                    for (int r = wave; r < bh; r += nwaves)
+                        for (int k = lane; k < ndw; k += 64) {
+                            const uint32_t d = zd[r * zpd + k];
+                            const int lo = (int)(int16_t)(d & 0xFFFFu), hi = (int)(int16_t)(d >> 16);
+                            zmin = min(zmin, min(lo, hi));
+                            zmax = max(zmax, max(lo, hi));
+                        }
+                } else {
+                    // four rows per wavefront and two 64-post chunks per row
+                    // in flight before the LDS writes
+                    for (int row = wave; row < bh; row += 4 * nwaves) {
+                        const int16_t *sp[4];
+                        int rb[4];
+                        bool rv[4];
 #pragma unroll
-                        for (int u = 0; u < 4; u++)
+                        for (int u = 0; u < 4; u++) {
+                            const int r = row + u * nwaves;
+                            rv[u] = r < bh;
+                            sp[u] = z + (gy0 + (rv[u] ? r : 0)) * ld + gx0;
+                            rb[u] = r * 2 * zpd + c0;
+                        }
+                        for (int cc = lane; cc < bw; cc += 128) {
+                            int v[4][2];
 #pragma unroll
-                            for (int h = 0; h < 2; h++) {
-                                const int col = c0 + 64 * h;
-                                v[u][h] = rv[u] && col < bw ? (int)sp[u][col] : 0;
-                            }
+                            for (int u = 0; u < 4; u++)
 #pragma unroll
-                        for (int u = 0; u < 4; u++)
-#pragma unroll
-                            for (int h = 0; h < 2; h++) {
-                                const int col = c0 + 64 * h;
-                                if (rv[u] && col < bw) {
-                                    zq[rb[u] + col * CS] = (int16_t)v[u][h];
-                                    zmin = min(zmin, v[u][h]);
-                                    zmax = max(zmax, v[u][h]);
+                                for (int h = 0; h < 2; h++) {
+                                    const int col = cc + 64 * h;
+                                    v[u][h] = rv[u] && col < bw ? (int)sp[u][col] : 0;
                                 }
-                            }
+#pragma unroll
+                            for (int u = 0; u < 4; u++)
+#pragma unroll
+                                for (int h = 0; h < 2; h++) {
+                                    const int col = cc + 64 * h;
+                                    if (rv[u] && col < bw) {
+                                        zq[rb[u] + col] = (int16_t)v[u][h];
+                                        zmin = min(zmin, v[u][h]);
+                                        zmax = max(zmax, v[u][h]);
+                                    }
+                                }
+                        }
                     }
                 }
                 zmin = wave_min_i32(zmin);
@@ -475,7 +501,19 @@ __global__ void viewshed_kernel(const int16_t *__restrict__ z, int64_t nrows, in
                 }
                 long long D = max((long long)gmax - E, (long long)E - gmin) + o.h_r;
                 bool narrow = D * R < (1ll << 23) && D * R * R < (1ll << 31);
-                LdsSrc src{zq};
+                // the observer's post in the staged box, and the steps of local
+                // u and v (elements; x is +1, y is +2*zpd)
+                const int zo_el = (int)(y - gy0) * 2 * zpd + (int)(x - gxe);
+                const int sx = 1, sy = 2 * zpd;
+                int su, sv;
+                switch (qd) {
+                case 0: su = sx;  sv = sy;  break;  // (u, v) = ( x,  y)
+                case 1: su = sy;  sv = -sx; break;  // (u, v) = ( y, -x)
+                case 2: su = -sx; sv = -sy; break;  // (u, v) = (-x, -y)
+                default: su = -sy; sv = sx; break;  // (u, v) = (-y,  x)
+                }
+                LdsSrc src{zq + zo_el};
+                const int zo_addr = zq_addr + 2 * zo_el;
                 const int nrays = Q.eu + Q.ev;
                 // threads take the boundary cells from both ends inwards: the
                 // near-axis rays (longest) fill the full wavefronts, and the
@@ -486,9 +524,10 @@ __global__ void viewshed_kernel(const int16_t *__restrict__ z, int64_t nrows, in
                     int du, dv;
                     ray_target(Q, rho, du, dv);
                     if (narrow)
-                        sweep_lds_narrow(zq_addr, zp, bm, P0, Q.bu, Q.bv, du, dv, R2, E, o.h_r);
+                        sweep_lds_narrow(zo_addr, 2 * su, 2 * sv, bm, P0, Q.bu, Q.bv, du, dv, R2,
+                                         E, o.h_r);
                     else
-                        sweep<false, false>(src, 1, zp, bm, P0, Q.bu, Q.bv, du, dv, R2, E, o.h_r);
+                        sweep<false, false>(src, su, sv, bm, P0, Q.bu, Q.bv, du, dv, R2, E, o.h_r);
                 }
                 __syncthreads();
             }
@@ -586,9 +625,11 @@ int viewshed_launch(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
         return rc;
     if (grid <= 0)
         return SITING_OK;
+    // direct HBM-to-LDS staging needs dword-aligned rows that hold whole dwords
+    const int dma = ld % 2 == 0 && ncols % 2 == 0 && reinterpret_cast<uintptr_t>(z) % 4 == 0;
     hipLaunchKernelGGL(viewshed_kernel, dim3((unsigned)grid), dim3(64 * sc.waves), (size_t)lds, s,
                        z, nrows, ncols, ld, obs, n, offsets, order, sink, bitmaps, visible, cells,
-                       queue, rmax, stage);
+                       queue, rmax, stage, dma);
     return check_launch("viewshed_kernel");
 }
 

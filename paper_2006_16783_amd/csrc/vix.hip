@@ -564,8 +564,9 @@ static int vix_launch(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld
         return SITING_E_UNSUPPORTED;
     }
     const int tile_bytes = use_lds ? (int)((((int64_t)(T + 2 * halo) * (T + 2 * halo + 2) * 2) + 15) & ~15ll) : 0;
-    // direct terrain-to-LDS loads need dword-aligned post pairs in every row
-    const int dma = (ld % 2 == 0) && ((uintptr_t)z % 4 == 0);
+    // direct HBM-to-LDS staging reads whole dwords: rows must start dword-aligned
+    // and hold an even number of posts, so that no dword passes a row's end
+    const int dma = (ld % 2 == 0) && (ncols % 2 == 0) && ((uintptr_t)z % 4 == 0);
     const size_t lds = (size_t)tile_bytes + queue_bytes;
     hipStream_t s = as_stream(stream);
     if (stats) {

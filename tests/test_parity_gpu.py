@@ -126,6 +126,23 @@ def test_viewshed_uneven_clipped(S, orc, seed, roi, height, shape):
     assert (got == want).all()
 
 
+@pytest.mark.parametrize("ld", [340, 341])
+def test_viewshed_strided_terrain(S, orc, ld):
+    # a 300x330 terrain inside wider rows: an even leading dimension stages the
+    # quadrants straight from HBM into LDS, an odd one through registers
+    _say("viewshed strided", ld)
+    z = _terrain(300, 2.4, 1500, 13, ncols=330)
+    big = torch.zeros((300, ld), dtype=torch.int16, device="cuda")
+    big[:, :330] = torch.from_numpy(z).cuda()
+    from synth import uniform_observers
+    obs = uniform_observers(300, 330, 120, 13, roi=(10, 90), height=(0, 40))
+    off = S.siting_viewshed_layout(obs, 300, 330)
+    bm = S.siting_viewshed_batch(big[:, :330], S.observers_to_device(obs),
+                                 torch.from_numpy(off).cuda(), 90)
+    want, _ = orc.viewshed(z, obs)
+    assert (_u64(bm)[:off[-1]] == want).all()
+
+
 def test_viewshed_every_schedule_same_bits(S, orc):
     from synth import uniform_observers
     z = _terrain(500, 2.4, 2000, 8)
