@@ -8,12 +8,13 @@
 //  * The observer's window bitmap lives in LDS (rows x words, a row pitch of
 //    an odd number of dwords so column-wise marks hit distinct banks) and is
 //    written to HBM once, coalesced, in the global word alignment.
-//  * The window is swept one quadrant at a time.  Each quadrant's rays read
-//    only posts inside that quadrant, so a workgroup stages a (R+2)^2 int16
-//    quadrant in LDS (rotated into a common local frame, so one ray routine
-//    serves all four), instead of the (2R+1)^2 window: 4x less LDS, 4x more
-//    resident workgroups.  Observers above the schedule's stage_rmax read the
-//    terrain straight from global memory (L2 / Infinity Cache) instead.
+//  * The window is swept one half at a time (upper: quadrants 0 and 1, lower:
+//    2 and 3).  A quadrant's rays read only posts inside it, so a workgroup
+//    stages a half-window ((R+1) x (2R+1) int16) in LDS, half the window's LDS,
+//    and sweeps both quadrants' rays together (about 4R rays, so the last
+//    wavefront of a pass is rarely nearly empty).  Observers above the
+//    schedule's stage_rmax read the terrain from global memory (L2 / Infinity
+//    Cache) instead.
 //  * One ray per lane; consecutive lanes take consecutive boundary cells, so
 //    a wavefront's rays have similar lengths and similar LDS rows.
 //  * Exact integer slopes.  The per-quadrant elevation range bounds every
@@ -315,15 +316,15 @@ __host__ __device__ __forceinline__ int bm_bytes(int rmax)
 {
     return (2 * rmax + 1) * bm_pitch_dw(rmax) * 4;
 }
-// A staged quadrant box (at most rmax+1 rows of rmax+1 posts) keeps the
+// A staged half-window (at most rmax+1 rows of 2*rmax+1 posts) keeps the
 // terrain's orientation; its rows start at an even terrain column, so a row
-// spans at most rmax+2 posts, and an odd dword pitch puts a column's posts in
+// spans at most 2*rmax+2 posts, and an odd dword pitch puts a column's posts in
 // distinct banks.  A ray whose line meets a post exactly still reads the next
 // post along the minor axis (with weight zero), which can lie one row past the
 // box: one spare row keeps that read inside the allocation.
 __host__ __device__ __forceinline__ int zq_pitch_dw(int rmax)
 {
-    return ((rmax + 3) >> 1) | 1;
+    return (rmax + 1) | 1;
 }
 __host__ __device__ __forceinline__ int zq_bytes(int rmax)
 {
@@ -405,21 +406,20 @@ __global__ void viewshed_kernel(const int16_t *__restrict__ z, int64_t nrows, in
             atomicOr(&bm[P0 >> 5], 1u << (P0 & 31));
 
         if (R <= stage_rmax) {
-            for (int qd = 0; qd < 4; qd++) {
-                Quadrant Q = make_quadrant(qd, ex_p, ex_m, ey_p, ey_m, BP, (int)ld);
-                if (Q.eu < 1)
+            for (int half = 0; half < 2; half++) {
+                // quadrants qa, qb = 0, 1 (rows y .. y+ey_p) or 2, 3 (rows
+                // y-ey_m .. y); columns x-ex_m .. x+ex_p
+                const int qa = 2 * half, qb = qa + 1;
+                const Quadrant QA = make_quadrant(qa, ex_p, ex_m, ey_p, ey_m, BP, (int)ld);
+                const Quadrant QB = make_quadrant(qb, ex_p, ex_m, ey_p, ey_m, BP, (int)ld);
+                const int nA = QA.eu >= 1 ? QA.eu + QA.ev : 0;
+                const int nB = QB.eu >= 1 ? QB.eu + QB.ev : 0;
+                if (nA + nB == 0)
                     continue;
-                // stage local (u, v) in [0, eu] x [0, ev] from the quadrant's
-                // global box, row by row (coalesced global reads)
-                int64_t gx0, gx1, gy0, gy1;
-                switch (qd) {
-                case 0: gx0 = x;         gx1 = x + Q.eu; gy0 = y;         gy1 = y + Q.ev; break;
-                case 1: gx0 = x - Q.ev;  gx1 = x;        gy0 = y;         gy1 = y + Q.eu; break;
-                case 2: gx0 = x - Q.eu;  gx1 = x;        gy0 = y - Q.ev;  gy1 = y;        break;
-                default: gx0 = x;        gx1 = x + Q.ev; gy0 = y - Q.eu;  gy1 = y;        break;
-                }
-                // stage the quadrant's box in the terrain's orientation, its
-                // rows from the even column gxe
+                const int64_t gx0 = x - ex_m, gx1 = x + ex_p;
+                const int64_t gy0 = half ? y - ey_m : y, gy1 = half ? y : y + ey_p;
+                // stage the half-window in the terrain's orientation, its rows
+                // from the even column gxe
                 int zmin = 32767, zmax = -32768;
                 const int bw = (int)(gx1 - gx0 + 1), bh = (int)(gy1 - gy0 + 1);
                 const int64_t gxe = gx0 & ~(int64_t)1;
@@ -501,26 +501,32 @@ __global__ void viewshed_kernel(const int16_t *__restrict__ z, int64_t nrows, in
                 }
                 long long D = max((long long)gmax - E, (long long)E - gmin) + o.h_r;
                 bool narrow = D * R < (1ll << 23) && D * R * R < (1ll << 31);
-                // the observer's post in the staged box, and the steps of local
-                // u and v (elements; x is +1, y is +2*zpd)
+                // the observer's post in the staged box, and the steps of each
+                // quadrant's local u and v (elements; x is +1, y is +2*zpd):
+                //   0: (u, v) = (x, y)   1: (y, -x)   2: (-x, -y)   3: (-y, x)
                 const int zo_el = (int)(y - gy0) * 2 * zpd + (int)(x - gxe);
-                const int sx = 1, sy = 2 * zpd;
-                int su, sv;
-                switch (qd) {
-                case 0: su = sx;  sv = sy;  break;  // (u, v) = ( x,  y)
-                case 1: su = sy;  sv = -sx; break;  // (u, v) = ( y, -x)
-                case 2: su = -sx; sv = -sy; break;  // (u, v) = (-x, -y)
-                default: su = -sy; sv = sx; break;  // (u, v) = (-y,  x)
-                }
+                const int sy = 2 * zpd;
                 LdsSrc src{zq + zo_el};
                 const int zo_addr = zq_addr + 2 * zo_el;
-                const int nrays = Q.eu + Q.ev;
+                // rays of the two quadrants alternate, and within a quadrant
                 // threads take the boundary cells from both ends inwards: the
-                // near-axis rays (longest) fill the full wavefronts, and the
-                // partial last one gets the near-diagonal rays, which leave
-                // the disk first
-                for (int t = tid; t < nrays; t += nthreads) {
-                    const int rho = (t & 1) ? nrays - 1 - (t >> 1) : (t >> 1);
+                // near-axis rays (longest) fill the first wavefronts, and the
+                // last one gets near-diagonal rays, which leave the disk first
+                const int m2 = 2 * min(nA, nB);
+                for (int t = tid; t < nA + nB; t += nthreads) {
+                    int qs, idx;
+                    if (t < m2) {
+                        qs = t & 1;
+                        idx = t >> 1;
+                    } else {
+                        qs = nA > nB ? 0 : 1;
+                        idx = t - m2 + (m2 >> 1);
+                    }
+                    const Quadrant &Q = qs ? QB : QA;
+                    const int nq = qs ? nB : nA;
+                    const int rho = (idx & 1) ? nq - 1 - (idx >> 1) : (idx >> 1);
+                    const int su = half ? (qs ? -sy : -1) : (qs ? sy : 1);
+                    const int sv = half ? (qs ? 1 : -sy) : (qs ? -1 : sy);
                     int du, dv;
                     ray_target(Q, rho, du, dv);
                     if (narrow)
@@ -637,9 +643,11 @@ int viewshed_default_schedule(int32_t rmax, siting_schedule *sc)
 {
     const int budget = 160 * 1024;
     sc->reserved = 0;
-    sc->waves = 4;
     int lds_staged = lds_bytes_for(rmax, rmax);
     if (rmax <= 160 && lds_staged <= std::min(budget, viewshed_max_dynamic_lds())) {
+        // a half-window has about 4R rays: enough wavefronts to sweep them in
+        // one pass, plus one, at most 8
+        sc->waves = std::max(2, std::min(8, (4 * rmax + 63) / 64 + 1));
         sc->stage_rmax = rmax;
         sc->groups_per_cu = std::max(1, std::min(8, budget / lds_staged));
     } else {
