@@ -217,45 +217,67 @@ __global__ __launch_bounds__(kGreedyThreads) void greedy_run(
     int64_t covered = 0;
     int pass = 0;
     while (t < max_obs && covered < target) {
-        // ---- global top key and the best key outside its block: every
-        // wavefront takes the two largest of its blocks, then the workgroup
-        uint64_t m1 = 0, m2 = 0;
-        int b1 = -1;
-        for (int b = wave + kGreedyWaves * lane; b < nblocks; b += kGreedyWaves * 64) {
-            const uint64_t v = bmax[b];
-            if (v > m1) {
-                m2 = m1;
-                m1 = v;
-                b1 = b;
-            } else if (v > m2) {
-                m2 = v;
-            }
-        }
-        const uint64_t wmax = wave_max_u64(m1);
-        const uint64_t owner = __ballot(m1 == wmax && wmax != 0);
-        const int ol = owner ? __ffsll((long long)owner) - 1 : 0;
-        const int wb = __builtin_amdgcn_readlane(b1, ol);
-        // the wavefront's second: the owner's own second or another lane's first
-        const uint64_t wsec = wave_max_u64(lane == ol ? m2 : m1);
-        if (lane == 0) {
-            s_t1[wave] = wmax;
-            s_t2[wave] = wsec;
-        }
-        __syncthreads();
-        uint64_t top = 0, second = 0;
+        // ---- global top key and the best key outside its block
+        uint64_t top = 0, second = 0, wmax = 0;
         int rank = 0;  // wavefronts holding a larger top than this one
-        int tw = 0;
-        for (int w2 = 0; w2 < kGreedyWaves; w2++) {
-            const uint64_t v = s_t1[w2];
-            if (v > top) {
-                top = v;
-                tw = w2;
+        int wb = 0;    // this wavefront's best block
+        if (pass == 0) {
+            // every wavefront scans all block maxima itself: no exchange and
+            // no barrier (the previous round's final barrier ordered the
+            // block maxima it wrote)
+            uint64_t m1 = 0, m2 = 0;
+            for (int b = lane; b < nblocks; b += 64) {
+                const uint64_t v = bmax[b];
+                if (v > m1) {
+                    m2 = m1;
+                    m1 = v;
+                } else if (v > m2) {
+                    m2 = v;
+                }
             }
-            rank += v > wmax;
-        }
-        for (int w2 = 0; w2 < kGreedyWaves; w2++) {
-            const uint64_t v = w2 == tw ? s_t2[w2] : s_t1[w2];
-            second = v > second ? v : second;
+            top = wave_max_u64(m1);
+            const uint64_t owner = __ballot(m1 == top && top != 0);
+            const int ol = owner ? __ffsll((long long)owner) - 1 : 0;
+            second = wave_max_u64(lane == ol ? m2 : m1);
+        } else {
+            // stale passes rank the wavefronts' tops: every wavefront takes
+            // the two largest of its blocks, then the workgroup
+            uint64_t m1 = 0, m2 = 0;
+            int b1 = -1;
+            for (int b = wave + kGreedyWaves * lane; b < nblocks; b += kGreedyWaves * 64) {
+                const uint64_t v = bmax[b];
+                if (v > m1) {
+                    m2 = m1;
+                    m1 = v;
+                    b1 = b;
+                } else if (v > m2) {
+                    m2 = v;
+                }
+            }
+            wmax = wave_max_u64(m1);
+            const uint64_t owner = __ballot(m1 == wmax && wmax != 0);
+            const int ol = owner ? __ffsll((long long)owner) - 1 : 0;
+            wb = __builtin_amdgcn_readlane(b1, ol);
+            // the wavefront's second: the owner's own second or another lane's first
+            const uint64_t wsec = wave_max_u64(lane == ol ? m2 : m1);
+            if (lane == 0) {
+                s_t1[wave] = wmax;
+                s_t2[wave] = wsec;
+            }
+            __syncthreads();
+            int tw = 0;
+            for (int w2 = 0; w2 < kGreedyWaves; w2++) {
+                const uint64_t v = s_t1[w2];
+                if (v > top) {
+                    top = v;
+                    tw = w2;
+                }
+                rank += v > wmax;
+            }
+            for (int w2 = 0; w2 < kGreedyWaves; w2++) {
+                const uint64_t v = w2 == tw ? s_t2[w2] : s_t1[w2];
+                second = v > second ? v : second;
+            }
         }
         const int64_t i = (int64_t)(0xFFFFFFFFull - (top & 0xFFFFFFFFull));
         const uint64_t g = top >> 32;
