@@ -8,21 +8,18 @@
 //   key[i]   (gain bound << 32) | (2^32-1 - i): one 64-bit max gives the
 //            largest bound with ties to the smallest index
 //   fresh[i] the round in which key[i] was last computed exactly
-//   bmax[b]  max of key[] over block b of 1024 candidates, with the round
+//   bmax[b]  max of key[] over block b of 512 candidates, with the round
 //            stamp of that maximum (LDS)
-// One persistent workgroup of 1024 threads runs every round.  The top key
-// and the best key outside the top's block come from the block maxima.  The
-// first pass of a round loads the top's window, its cumulative words and the
-// keys of its block together (one window word and one key per thread); a
-// stale top is re-evaluated, popcount(V & ~C), and taken at once if its exact
-// key still exceeds every other key (the stated bound: gains only shrink), in
-// which case its window is ORed into C from the words already loaded.  If it
-// does not, later passes re-evaluate in parallel: the k-th involves the 2^k
-// wavefronts with the best tops (at most 16), wavefront w owning the blocks
-// b = w (mod 16).  The global top is always among them, so every pass makes
-// progress; sparse candidate sets need one pass per round, dense ones (where
-// a selection leaves many stale neighbours on top) converge in a few wide
-// passes.
+// One wavefront runs every round, so a round needs no barrier: the top key
+// and the best key outside the top's block come from the block maxima; the
+// top's window words, its cumulative words and the keys of its block are then
+// loaded together (16 window words and 8 keys per lane); a stale top is
+// re-evaluated, popcount(V & ~C), and taken at once if its exact key still
+// exceeds every other key (the stated bound: gains only shrink), its window
+// ORed into C from the words already in registers.  Otherwise its new key goes
+// back and the next round pops the new top: each round either selects an
+// observer or lowers a key, and a fresh top (re-evaluated since the last
+// selection) is exact and taken without loading its gain again.
 #include <algorithm>
 
 #include "common.hpp"
@@ -30,10 +27,10 @@
 namespace siting {
 namespace {
 
-constexpr int kGreedyThreads = 1024;
-constexpr int kGreedyWaves = kGreedyThreads / 64;
-constexpr int kGreedyBlock = 1024;   // candidates per bmax entry
-constexpr int kGreedyMaxBlocks = 16384;
+constexpr int kGreedyBlock = 512;    // candidates per bmax entry
+constexpr int kGreedyKeys = kGreedyBlock / 64;  // keys of a block per lane
+constexpr int kGreedyWords = 16;     // window words per lane per batch
+constexpr int kGreedyMaxBlocks = 8192;
 
 // popcount totals of a window: at most (2*16383+1)^2 < 2^31 bits
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) { return wave_sum_u32((uint32_t)v); }
@@ -99,39 +96,6 @@ __global__ __launch_bounds__(256) void greedy_init(const uint64_t *__restrict__ 
         key[i] = (g << 32) | (0xFFFFFFFFull - (uint64_t)i);
 }
 
-// gain of candidate j against C: popcount(V_j & ~C) over its window, one
-// wavefront (result in every lane); eight words per lane are loaded before
-// any is used, so a window costs a few memory round trips
-__device__ __forceinline__ uint64_t wave_gain(const uint64_t *__restrict__ bitmaps,
-                                              const int64_t *__restrict__ offsets,
-                                              const siting_observer &o, int64_t j, int64_t nrows,
-                                              int64_t ncols, const uint64_t *C, int64_t W,
-                                              int lane)
-{
-    const Win w = window_of(o, nrows, ncols);
-    const uint64_t *v = bitmaps + offsets[j];
-    const int words = w.rows * w.nw;
-    uint64_t cnt = 0;
-    for (int e0 = 0; e0 < words; e0 += 8 * 64) {
-        uint64_t vv[8], cc[8];
-#pragma unroll
-        for (int u = 0; u < 8; u++) {
-            const int e = e0 + u * 64 + lane;
-            vv[u] = 0;
-            cc[u] = 0;
-            if (e < words) {
-                const int row = e / w.nw, c = e - row * w.nw;
-                vv[u] = v[e];
-                cc[u] = C[(w.ylo + row) * W + w.w0 + c];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < 8; u++)
-            cnt += __popcll(vv[u] & ~cc[u]);
-    }
-    return wave_sum_u64(cnt);
-}
-
 // max key of block b and that key's stamp, one wavefront (results in every
 // lane); the key of candidate `ov` (if in the block) is taken as `ok` with
 // stamp `of` instead of its stored value
@@ -166,227 +130,235 @@ __device__ __forceinline__ void wave_block_max(const uint64_t *key, const int32_
     bfr = __builtin_amdgcn_readlane(f, owner ? __ffsll((long long)owner) - 1 : 0);
 }
 
-__global__ __launch_bounds__(kGreedyThreads) void greedy_run(
+// block maxima of the initial keys, one wavefront per block
+__global__ __launch_bounds__(64) void greedy_blocks(const uint64_t *__restrict__ key,
+                                                    const int32_t *__restrict__ fresh, int64_t n,
+                                                    uint64_t *__restrict__ bmax_g,
+                                                    int32_t *__restrict__ bfr_g)
+{
+    const int b = blockIdx.x, lane = threadIdx.x;
+    uint64_t v;
+    int32_t f;
+    wave_block_max(key, fresh, n, b, lane, -1, 0, 0, v, f);
+    if (lane == 0) {
+        bmax_g[b] = v;
+        bfr_g[b] = f;
+    }
+}
+
+__global__ __launch_bounds__(64) void greedy_run(
     const uint64_t *__restrict__ bitmaps, const int64_t *__restrict__ offsets,
     const siting_observer *__restrict__ obs, int64_t n, int64_t nrows, int64_t ncols,
     int32_t max_obs, int64_t target, uint64_t *C, int64_t *__restrict__ selected,
-    int64_t *__restrict__ gains, int32_t *__restrict__ nselected, uint64_t *key, int32_t *fresh)
+    int64_t *__restrict__ gains, int32_t *__restrict__ nselected, uint64_t *key, int32_t *fresh,
+    const uint64_t *__restrict__ bmax_g, const int32_t *__restrict__ bfr_g)
 {
     // block maxima of the keys and the round stamps of those maxima
     extern __shared__ uint64_t bmax[];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lane = threadIdx.x;
     const int64_t W = (ncols + 63) >> 6;
     const int nblocks = (int)((n + kGreedyBlock - 1) / kGreedyBlock);
     int32_t *bfr = reinterpret_cast<int32_t *>(bmax + nblocks);
-    // per-wavefront partials: s_t* for the top selection, s_a/s_b for the
-    // pass's reduction (separate, so neither needs a barrier before reuse)
-    __shared__ uint64_t s_t1[kGreedyWaves], s_t2[kGreedyWaves];
-    __shared__ uint64_t s_a[kGreedyWaves], s_b[kGreedyWaves];
-
-    // workgroup sum of a and max of b in one exchange (results in every
-    // thread); s_a/s_b were last read before the previous round's final
-    // barrier
-    auto wg_sum_max = [&](uint64_t a, uint64_t b, uint64_t &sa, uint64_t &mb) {
-        a = wave_sum_u64(a);
-        b = wave_max_u64(b);
-        if (lane == 0) {
-            s_a[wave] = a;
-            s_b[wave] = b;
-        }
-        __syncthreads();
-        sa = 0;
-        mb = 0;
-        for (int w2 = 0; w2 < kGreedyWaves; w2++) {
-            sa += s_a[w2];
-            mb = s_b[w2] > mb ? s_b[w2] : mb;
-        }
-    };
-
-    for (int b = wave; b < nblocks; b += kGreedyWaves) {
-        uint64_t v;
-        int32_t f;
-        wave_block_max(key, fresh, n, b, lane, -1, 0, 0, v, f);
-        if (lane == 0) {
-            bmax[b] = v;
-            bfr[b] = f;
-        }
+    for (int b = lane; b < nblocks; b += 64) {
+        bmax[b] = bmax_g[b];
+        bfr[b] = bfr_g[b];
     }
+    // one wavefront: LDS accesses run in order; the barrier only keeps the
+    // compiler from moving them
     __syncthreads();
 
     int32_t t = 0;
     int64_t covered = 0;
-    int pass = 0;
+    // the next round's top is known when a round ends (the larger of the best
+    // key outside the round's block and that block's new maximum): its record
+    // and its block's keys are loaded then, while the next top selection runs
+    int64_t pf_i = -1;
+    siting_observer pf_o{0, 0, 0, 0, 0};
+    int64_t pf_off = 0;
+    uint64_t pf_k[kGreedyKeys];
+    int32_t pf_f[kGreedyKeys];
+    auto load_block = [&](int b, int64_t skip, uint64_t *kk, int32_t *ff) {
+#pragma unroll
+        for (int u = 0; u < kGreedyKeys; u++) {
+            const int64_t j = (int64_t)b * kGreedyBlock + u * 64 + lane;
+            kk[u] = j < n && j != skip ? key[j] : 0;
+            ff[u] = j < n ? fresh[j] : 0;
+        }
+    };
     while (t < max_obs && covered < target) {
-        // ---- global top key and the best key outside its block
-        uint64_t top = 0, second = 0, wmax = 0;
-        int rank = 0;  // wavefronts holding a larger top than this one
-        int wb = 0;    // this wavefront's best block
-        if (pass == 0) {
-            // every wavefront scans all block maxima itself: no exchange and
-            // no barrier (the previous round's final barrier ordered the
-            // block maxima it wrote)
-            uint64_t m1 = 0, m2 = 0;
-            for (int b = lane; b < nblocks; b += 64) {
-                const uint64_t v = bmax[b];
-                if (v > m1) {
-                    m2 = m1;
-                    m1 = v;
-                } else if (v > m2) {
-                    m2 = v;
-                }
-            }
-            top = wave_max_u64(m1);
-            const uint64_t owner = __ballot(m1 == top && top != 0);
-            const int ol = owner ? __ffsll((long long)owner) - 1 : 0;
-            second = wave_max_u64(lane == ol ? m2 : m1);
-        } else {
-            // stale passes rank the wavefronts' tops: every wavefront takes
-            // the two largest of its blocks, then the workgroup
-            uint64_t m1 = 0, m2 = 0;
-            int b1 = -1;
-            for (int b = wave + kGreedyWaves * lane; b < nblocks; b += kGreedyWaves * 64) {
-                const uint64_t v = bmax[b];
-                if (v > m1) {
-                    m2 = m1;
-                    m1 = v;
-                    b1 = b;
-                } else if (v > m2) {
-                    m2 = v;
-                }
-            }
-            wmax = wave_max_u64(m1);
-            const uint64_t owner = __ballot(m1 == wmax && wmax != 0);
-            const int ol = owner ? __ffsll((long long)owner) - 1 : 0;
-            wb = __builtin_amdgcn_readlane(b1, ol);
-            // the wavefront's second: the owner's own second or another lane's first
-            const uint64_t wsec = wave_max_u64(lane == ol ? m2 : m1);
-            if (lane == 0) {
-                s_t1[wave] = wmax;
-                s_t2[wave] = wsec;
-            }
-            __syncthreads();
-            int tw = 0;
-            for (int w2 = 0; w2 < kGreedyWaves; w2++) {
-                const uint64_t v = s_t1[w2];
-                if (v > top) {
-                    top = v;
-                    tw = w2;
-                }
-                rank += v > wmax;
-            }
-            for (int w2 = 0; w2 < kGreedyWaves; w2++) {
-                const uint64_t v = w2 == tw ? s_t2[w2] : s_t1[w2];
-                second = v > second ? v : second;
+        // ---- the top key and the best key outside its block
+        uint64_t m1 = 0, m2 = 0;
+        for (int b = lane; b < nblocks; b += 64) {
+            const uint64_t v = bmax[b];
+            if (v > m1) {
+                m2 = m1;
+                m1 = v;
+            } else if (v > m2) {
+                m2 = v;
             }
         }
+        const uint64_t top = wave_max_u64(m1);
+        const uint64_t owner = __ballot(m1 == top && top != 0);
+        const int ol = owner ? __ffsll((long long)owner) - 1 : 0;
+        const uint64_t second = wave_max_u64(lane == ol ? m2 : m1);
         const int64_t i = (int64_t)(0xFFFFFFFFull - (top & 0xFFFFFFFFull));
         const uint64_t g = top >> 32;
         if (top == 0 || i >= n)
             break;  // unreachable with n >= 1
         const int bi = (int)(i / kGreedyBlock);
-        // (bmax/bfr change only after the pass's reduction barrier)
         const int32_t fr = bfr[bi];
-        if (fr == t || pass == 0) {
-            // Re-evaluate the top if it is stale (the whole workgroup, one
-            // window word per thread), and take it if it is fresh or stays
-            // above every other key.  The window, the cumulative words and the
-            // top's block of keys are loaded together.
-            const bool stale = fr != t;
-            if (!stale && g == 0)
-                break;
-            const siting_observer o = obs[i];
-            const bool valid = obs_ok(o, nrows, ncols);
-            const int64_t j = (int64_t)bi * kGreedyBlock + tid;
-            const uint64_t kj = j < n ? key[j] : 0;
-            const int32_t fj = j < n ? fresh[j] : 0;
-            Win w{0, 0, 0, 0};
-            const uint64_t *v = bitmaps;
-            if (valid) {
-                w = window_of(o, nrows, ncols);
-                v = bitmaps + offsets[i];
+        const bool stale = fr != t;
+        if (!stale && g == 0)
+            break;  // no candidate gains anything
+        // ---- the top's window, its cumulative words and its block's keys,
+        // loaded together
+        siting_observer o;
+        int64_t off;
+        uint64_t kk[kGreedyKeys];
+        int32_t ff[kGreedyKeys];
+        if (i == pf_i) {
+            o = pf_o;
+            off = pf_off;
+#pragma unroll
+            for (int u = 0; u < kGreedyKeys; u++) {
+                kk[u] = pf_k[u];
+                ff[u] = pf_f[u];
             }
-            const int words = w.rows * w.nw;
-            // this thread's first window word stays in registers for the OR
-            uint64_t v0 = 0, c0 = 0;
-            uint64_t cnt = 0;
-            for (int e = tid; e < words; e += kGreedyThreads) {
-                const int row = e / w.nw, c = e - row * w.nw;
-                const uint64_t ve = v[e], ce = C[(w.ylo + row) * W + w.w0 + c];
-                if (e == tid) {
-                    v0 = ve;
-                    c0 = ce;
+        } else {
+            o = obs[i];
+            off = offsets[i];
+            load_block(bi, i, kk, ff);
+        }
+        const bool valid = obs_ok(o, nrows, ncols);
+        Win w{0, 0, 0, 0};
+        const uint64_t *v = bitmaps;
+        if (valid) {
+            w = window_of(o, nrows, ncols);
+            v = bitmaps + off;
+        }
+        const int words = w.rows * w.nw;
+        // the first batch of window words stays in registers for the OR; the
+        // word index e = 64u + lane walks the window's rows without division
+        const int dq = 64 / (w.nw > 0 ? w.nw : 1), dr = 64 - dq * w.nw;
+        int row0 = lane / (w.nw > 0 ? w.nw : 1), col0 = lane - row0 * w.nw;
+        int64_t cix[kGreedyWords];
+        uint64_t vv[kGreedyWords], cc[kGreedyWords];
+        {
+            int row = row0, col = col0;
+#pragma unroll
+            for (int u = 0; u < kGreedyWords; u++) {
+                cix[u] = (w.ylo + row) * W + w.w0 + col;
+                col += dr;
+                row += dq;
+                if (col >= w.nw) {
+                    col -= w.nw;
+                    row++;
                 }
-                cnt += __popcll(ve & ~ce);
             }
-            // one exchange: the exact gain (when stale) and the largest key of
-            // the top's block other than the top's own
-            const uint64_t kj_ex = j == i ? 0 : kj;
-            uint64_t gsum, bo;
-            wg_sum_max(stale ? cnt : 0, kj_ex, gsum, bo);
-            const uint64_t gain = stale ? gsum : g;
-            const uint64_t nk = (gain << 32) | (0xFFFFFFFFull - (uint64_t)i);
-            // lazy greedy: a fresh gain at least every other key (stale or
-            // not) is the plain greedy choice; keys are unique
-            const bool take = gain > 0 && (!stale || (nk > second && nk > bo));
-            // after this pass: nk for i, or a zero gain once i is taken
-            const uint64_t ki = take ? (0xFFFFFFFFull - (uint64_t)i) : nk;
-            const int32_t fi = take ? t + 1 : t;
-            const uint64_t bm2 = ki > bo ? ki : bo;
-            // the holder of the block's new maximum records it (another
-            // candidate's, or i's own new key)
-            if ((bm2 == bo && kj_ex == bo && bo != 0) || (bm2 == ki && j == i)) {
-                bmax[bi] = bm2;
-                bfr[bi] = j == i ? fi : fj;
+        }
+#pragma unroll
+        for (int u = 0; u < kGreedyWords; u++) {
+            const int e = u * 64 + lane;
+            vv[u] = 0;
+            cc[u] = 0;
+            if (e < words) {
+                vv[u] = v[e];
+                cc[u] = C[cix[u]];
             }
-            if (take) {
-                for (int e = tid; e < words; e += kGreedyThreads) {
+        }
+        uint64_t cnt = 0;
+#pragma unroll
+        for (int u = 0; u < kGreedyWords; u++)
+            cnt += __popcll(vv[u] & ~cc[u]);
+        // windows above 64 * kGreedyWords words: the rest in further batches
+        for (int e0 = 64 * kGreedyWords; stale && e0 < words; e0 += 64 * kGreedyWords) {
+            uint64_t v2[kGreedyWords], c2[kGreedyWords];
+#pragma unroll
+            for (int u = 0; u < kGreedyWords; u++) {
+                const int e = e0 + u * 64 + lane;
+                v2[u] = 0;
+                c2[u] = 0;
+                if (e < words) {
                     const int row = e / w.nw, c = e - row * w.nw;
-                    uint64_t *ce = &C[(w.ylo + row) * W + w.w0 + c];
-                    *ce = e == tid ? (c0 | v0) : (*ce | v[e]);
+                    v2[u] = v[e];
+                    c2[u] = C[(w.ylo + row) * W + w.w0 + c];
                 }
             }
-            if (j == i) {
-                key[i] = ki;
-                fresh[i] = fi;
+#pragma unroll
+            for (int u = 0; u < kGreedyWords; u++)
+                cnt += __popcll(v2[u] & ~c2[u]);
+        }
+        // the largest key of the top's block other than the top's own
+        uint64_t kb = 0;
+        int32_t fb = 0;
+#pragma unroll
+        for (int u = 0; u < kGreedyKeys; u++) {
+            if (kk[u] > kb) {
+                kb = kk[u];
+                fb = ff[u];
             }
-            if (tid == 0 && take) {
+        }
+        const uint64_t bo = wave_max_u64(kb);
+        const uint64_t bown = __ballot(kb == bo && bo != 0);
+        const int32_t fbo = __builtin_amdgcn_readlane(fb, bown ? __ffsll((long long)bown) - 1 : 0);
+        const uint64_t gain = stale ? wave_sum_u64(cnt) : g;
+        const uint64_t nk = (gain << 32) | (0xFFFFFFFFull - (uint64_t)i);
+        // lazy greedy: a fresh gain at least every other key (stale or not)
+        // is the plain greedy choice; keys are unique
+        const bool take = gain > 0 && (!stale || (nk > second && nk > bo));
+        // after this round: nk for i, or a zero gain once i is taken
+        const uint64_t ki = take ? (0xFFFFFFFFull - (uint64_t)i) : nk;
+        const int32_t fi = take ? t + 1 : t;
+        if (lane == 0) {
+            const bool mine = ki > bo;
+            bmax[bi] = mine ? ki : bo;
+            bfr[bi] = mine ? fi : fbo;
+            key[i] = ki;
+            fresh[i] = fi;
+            if (take) {
                 selected[t] = i;
                 gains[t] = (int64_t)gain;
             }
-            if (take) {
-                covered += (int64_t)gain;
-                t++;
-                pass = 0;
-            } else {
-                pass = 1;
+        }
+        if (take) {
+#pragma unroll
+            for (int u = 0; u < kGreedyWords; u++) {
+                const int e = u * 64 + lane;
+                if (e < words)
+                    C[cix[u]] = cc[u] | vv[u];
             }
-        } else {
-            // later stale passes: the k-th re-evaluates the tops of the 2^k
-            // best wavefronts in parallel, one wavefront each (up to 16)
-            const bool go = wmax != 0 && rank < (1 << pass);
-            pass = pass < 4 ? pass + 1 : 4;
-            // ---- this wavefront re-evaluates the top of its best block
-            const int64_t jj = (int64_t)(0xFFFFFFFFull - (wmax & 0xFFFFFFFFull));
-            if (go && bfr[wb] != t) {
-                const siting_observer o = obs[jj];
-                uint64_t gj = 0;
-                if (obs_ok(o, nrows, ncols))
-                    gj = wave_gain(bitmaps, offsets, o, jj, nrows, ncols, C, W, lane);
-                const uint64_t nkj = (gj << 32) | (0xFFFFFFFFull - (uint64_t)jj);
-                uint64_t bv;
-                int32_t bf;
-                wave_block_max(key, fresh, n, wb, lane, jj, nkj, t, bv, bf);
-                if (lane == 0) {
-                    key[jj] = nkj;
-                    fresh[jj] = t;
-                    bmax[wb] = bv;
-                    bfr[wb] = bf;
+            for (int e = 64 * kGreedyWords + lane; e < words; e += 64) {
+                const int row = e / w.nw, c = e - row * w.nw;
+                uint64_t *ce = &C[(w.ylo + row) * W + w.w0 + c];
+                *ce |= v[e];
+            }
+            covered += (int64_t)gain;
+            t++;
+        }
+        // the next top: the best key outside block bi or bi's new maximum
+        {
+            const uint64_t bnew = ki > bo ? ki : bo;
+            const uint64_t nx = second > bnew ? second : bnew;
+            const int64_t p = (int64_t)(0xFFFFFFFFull - (nx & 0xFFFFFFFFull));
+            pf_i = nx != 0 && p < n ? p : -1;
+            if (pf_i >= 0) {
+                pf_o = obs[pf_i];
+                pf_off = offsets[pf_i];
+                // keys of the next top's block; i's key and stamp as just set
+                load_block((int)(pf_i / kGreedyBlock), pf_i, pf_k, pf_f);
+#pragma unroll
+                for (int u = 0; u < kGreedyKeys; u++) {
+                    const int64_t j = (pf_i / kGreedyBlock) * kGreedyBlock + u * 64 + lane;
+                    if (j == i && j != pf_i) {  // the top's own key stays out
+                        pf_k[u] = ki;
+                        pf_f[u] = fi;
+                    }
                 }
             }
         }
         __syncthreads();
     }
-    if (tid == 0)
+    if (lane == 0)
         *nselected = t;
 }
 
@@ -401,7 +373,8 @@ extern "C" size_t siting_greedy_workspace_size(int64_t n)
 {
     if (n < 0)
         return 0;
-    return align256((size_t)n * 8) + align256((size_t)n * 4);
+    const size_t nb = (size_t)((n + kGreedyBlock - 1) / kGreedyBlock);
+    return align256((size_t)n * 8) + align256((size_t)n * 4) + align256(nb * 8) + align256(nb * 4);
 }
 
 extern "C" int siting_greedy(const uint64_t *bitmaps, const int64_t *offsets,
@@ -429,9 +402,14 @@ extern "C" int siting_greedy(const uint64_t *bitmaps, const int64_t *offsets,
         set_error("%s: %lld candidates exceed the supported maximum", fn, (long long)n);
         return SITING_E_UNSUPPORTED;
     }
-    uint64_t *key = reinterpret_cast<uint64_t *>(ws);
-    int32_t *fresh =
-        reinterpret_cast<int32_t *>(reinterpret_cast<char *>(ws) + align256((size_t)n * 8));
+    char *wsb = reinterpret_cast<char *>(ws);
+    uint64_t *key = reinterpret_cast<uint64_t *>(wsb);
+    wsb += align256((size_t)n * 8);
+    int32_t *fresh = reinterpret_cast<int32_t *>(wsb);
+    wsb += align256((size_t)n * 4);
+    uint64_t *bmax_g = reinterpret_cast<uint64_t *>(wsb);
+    wsb += align256((size_t)nblocks * 8);
+    int32_t *bfr_g = reinterpret_cast<int32_t *>(wsb);
     hipStream_t s = as_stream(stream);
     const int64_t W = (ncols + 63) / 64;
     const int64_t cwords = nrows * W;
@@ -444,8 +422,12 @@ extern "C" int siting_greedy(const uint64_t *bitmaps, const int64_t *offsets,
                        offsets, obs, n, nrows, ncols, key, fresh);
     if ((rc = check_launch("greedy_init")) != SITING_OK)
         return rc;
-    hipLaunchKernelGGL(greedy_run, dim3(1), dim3(kGreedyThreads), (size_t)nblocks * 12, s, bitmaps,
-                       offsets, obs, n, nrows, ncols, max_obs, target_cells, cumulative, selected,
-                       gains, nselected, key, fresh);
+    hipLaunchKernelGGL(greedy_blocks, dim3((unsigned)nblocks), dim3(64), 0, s, key, fresh, n,
+                       bmax_g, bfr_g);
+    if ((rc = check_launch("greedy_blocks")) != SITING_OK)
+        return rc;
+    hipLaunchKernelGGL(greedy_run, dim3(1), dim3(64), (size_t)nblocks * 12, s, bitmaps, offsets,
+                       obs, n, nrows, ncols, max_obs, target_cells, cumulative, selected, gains,
+                       nselected, key, fresh, bmax_g, bfr_g);
     return check_launch("greedy_run");
 }
