@@ -183,6 +183,14 @@ __device__ __forceinline__ int mad_i24(int a, int b, int c)
     return r;
 }
 
+// 24-bit signed multiply (full rate): a * b with |a|, |b| < 2^23.
+__device__ __forceinline__ int mul_i24(int a, int b)
+{
+    int r;
+    asm("v_mul_i32_i24 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
 typedef const int16_t __attribute__((address_space(3))) lds_i16;
 __device__ __forceinline__ int lds_read_i16(int addr)
 {
@@ -200,7 +208,10 @@ __device__ __forceinline__ int lds_read_i16(int addr)
 //  * the receiver's line is tested as T*J + h_r*n*J >= hN*k with one
 //    multiply-add (h_r*n < 2^23 in narrow mode);
 //  * post offsets are LDS byte addresses (zq_addr: the observer's post;
-//    zs_u, zs_v: the byte steps of local u and v in the staged quadrant).
+//    zs_u, zs_v: the byte steps of local u and v in the staged quadrant);
+//    the post's address and the marked cell's bit position advance together
+//    as one 64-bit value (bit position << 32 | address: both are
+//    non-negative, so one 64-bit add of the packed signed steps is exact).
 __device__ __forceinline__ void sweep_lds_narrow(int zq_addr, int zs_u, int zs_v, uint32_t *bm,
                                                  int P0, int bu, int bv, int du, int dv, int R2,
                                                  int E, int h_r)
@@ -250,13 +261,17 @@ __device__ __forceinline__ void sweep_lds_narrow(int zq_addr, int zs_u, int zs_v
         }
     }
     uint32_t eu = (uint32_t)e;
+    uint64_t pos = ((uint64_t)(uint32_t)bq << 32) | (uint32_t)zi;
+    const uint64_t d0 = (uint64_t)(((int64_t)bs_maj << 32) + zs_maj);
+    const uint64_t d1 = (uint64_t)(((int64_t)(bs_maj + bs_min) << 32) + (zs_maj + zs_min));
     int k = 2;
     for (; k <= ks; k++) {
         uint32_t e1;
         const bool w = __builtin_add_overflow(eu, (uint32_t)mn, &e1);
         eu = w ? e1 - (uint32_t)n : e1;
-        zi += zs_maj + (w ? zs_min : 0);
-        bq += bs_maj + (w ? bs_min : 0);
+        pos += w ? d1 : d0;
+        zi = (int)(uint32_t)pos;
+        bq = (int)(pos >> 32);
         const int ee = (int)eu;
         const int z0 = lds_read_i16(zi), z1 = lds_read_i16(zi + zs_min);
         const int Tk = mad_i24(z1 - z0, ee, mad_i24(z1, n, nEn));
@@ -269,7 +284,7 @@ __device__ __forceinline__ void sweep_lds_narrow(int zq_addr, int zs_u, int zs_v
         if (PT > B) {
             hN = Tk;
             hJ = k;
-            B = __mul24(Tk, k);
+            B = mul_i24(Tk, k);
         }
     }
     if (k > n)
@@ -281,8 +296,9 @@ __device__ __forceinline__ void sweep_lds_narrow(int zq_addr, int zs_u, int zs_v
         uint32_t e1;
         const bool w = __builtin_add_overflow(eu, (uint32_t)mn, &e1);
         eu = w ? e1 - (uint32_t)n : e1;
-        zi += zs_maj + (w ? zs_min : 0);
-        bq += bs_maj + (w ? bs_min : 0);
+        pos += w ? d1 : d0;
+        zi = (int)(uint32_t)pos;
+        bq = (int)(pos >> 32);
         q += w ? 1 : 0;
         k2 += 2 * k - 1;
         const int ee = (int)eu;
@@ -301,7 +317,7 @@ __device__ __forceinline__ void sweep_lds_narrow(int zq_addr, int zs_u, int zs_v
         if (PT > B) {
             hN = Tk;
             hJ = k;
-            B = __mul24(Tk, k);
+            B = mul_i24(Tk, k);
         }
     }
 }
