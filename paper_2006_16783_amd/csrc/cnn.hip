@@ -138,6 +138,7 @@ __global__ __launch_bounds__(64 * kFwdWaves) void cnn_fwd_kernel(FwdArgs A)
 
     // tile geometry
     int tw = kPatch, th = kPatch;  // tile width/height in posts
+    int tp = kPatch;               // tile row pitch (a multiple of 4 posts)
     int64_t ty0 = 0, tx0 = 0;      // global post of tile (0,0) (unclamped)
     int nloc = 1;                  // posts handled by this workgroup
     if (!kTrain) {
@@ -145,6 +146,7 @@ __global__ __launch_bounds__(64 * kFwdWaves) void cnn_fwd_kernel(FwdArgs A)
         // patches are centred on the highest post of each cell: up to
         // stride-1 posts past the cell corner
         tw = th = A.BL * A.stride + kPatch - 1;
+        tp = (tw + 3) & ~3;
         ty0 = bi * A.BL * A.stride - kPatch / 2;
         tx0 = bj * A.BL * A.stride - kPatch / 2;
         // stage the clamped tile once for the whole workgroup: rows by
@@ -172,7 +174,7 @@ __global__ __launch_bounds__(64 * kFwdWaves) void cnn_fwd_kernel(FwdArgs A)
                 for (int cc = 0; cc < 4; cc++) {
                     const int c = lane + 64 * cc;
                     if (r < th && c < tw)
-                        tile[r * tw + c] = v[u][cc];
+                        tile[r * tp + c] = v[u][cc];
                 }
             }
         }
@@ -216,7 +218,7 @@ __global__ __launch_bounds__(64 * kFwdWaves) void cnn_fwd_kernel(FwdArgs A)
             for (int e = lane; e < ss; e += 64) {
                 const int r = e / A.stride, c = e - r * A.stride;
                 if (li * A.stride + r < A.nrows && lj * A.stride + c < A.ncols) {
-                    const int v = tile[(py * A.stride + r + kPatch / 2) * tw +
+                    const int v = tile[(py * A.stride + r + kPatch / 2) * tp +
                                        px * A.stride + c + kPatch / 2];
                     const int key = ((v + 32768) << 12) | (4095 - e);
                     best = key > best ? key : best;
@@ -234,16 +236,32 @@ __global__ __launch_bounds__(64 * kFwdWaves) void cnn_fwd_kernel(FwdArgs A)
             or_ = py * A.stride + r;
             oc = px * A.stride + c;
         }
-        const int zc = tile[(or_ + kPatch / 2) * tw + oc + kPatch / 2];
+        const int zc = tile[(or_ + kPatch / 2) * tp + oc + kPatch / 2];
 
         // ---- conv1: one MFMA per output row oy (16 output columns)
 #pragma unroll 4
         for (int oy = 0; oy < 16; oy++) {
-            const int16_t *src = tile + (or_ + 4 * oy + hi) * tw + oc + 4 * lo;
+            const int16_t *src = tile + (or_ + 4 * oy + hi) * tp + oc + 4 * lo;
+            // the four posts as two dwords: rows start dword-aligned (tp is a
+            // multiple of 4), so a patch's reads are aligned when oc is even
+            // and otherwise take three dwords shifted by one post
+            uint32_t p01, p23;
+            if ((oc & 1) == 0) {
+                const uint32_t *q = reinterpret_cast<const uint32_t *>(src);
+                p01 = q[0];
+                p23 = q[1];
+            } else {
+                const uint32_t *q = reinterpret_cast<const uint32_t *>(src - 1);
+                const uint32_t d0 = q[0], d1 = q[1], d2 = q[2];
+                p01 = __builtin_amdgcn_alignbyte(d1, d0, 2);
+                p23 = __builtin_amdgcn_alignbyte(d2, d1, 2);
+            }
             // elevation differences in units of 256 m (exact power-of-two scale)
             constexpr float kScale = 0.00390625f;
-            const float v0 = (float)(src[0] - zc) * kScale, v1 = (float)(src[1] - zc) * kScale;
-            const float v2 = (float)(src[2] - zc) * kScale, v3 = (float)(src[3] - zc) * kScale;
+            const float v0 = (float)((int)(int16_t)(p01 & 0xFFFFu) - zc) * kScale;
+            const float v1 = (float)((int)(int16_t)(p01 >> 16) - zc) * kScale;
+            const float v2 = (float)((int)(int16_t)(p23 & 0xFFFFu) - zc) * kScale;
+            const float v3 = (float)((int)(int16_t)(p23 >> 16) - zc) * kScale;
             const s4 a = pack4(v0, v1, v2, v3);
             if (kTrain) {
                 uint16_t *ps = A.Pst + pid * 4096 + (4 * oy + hi) * 64 + 4 * lo;
@@ -847,7 +865,7 @@ extern "C" int siting_cnn_score_terrain(const float *params, const int16_t *z, i
     a.blocks_c = (a.lat_c + a.BL - 1) / a.BL;
     a.score = score;
     const int tw = a.BL * stride + kPatch - 1;
-    const size_t lds = kFwdWaves * kWaveLdsElems * 2 + (size_t)tw * tw * 2;
+    const size_t lds = kFwdWaves * kWaveLdsElems * 2 + (size_t)tw * ((tw + 3) & ~3) * 2;
     if ((int64_t)lds > kernel_max_dynamic_lds(reinterpret_cast<const void *>(&cnn_fwd_kernel<false>))) {
         set_error("%s: tile does not fit in LDS", fn);
         return SITING_E_UNSUPPORTED;
