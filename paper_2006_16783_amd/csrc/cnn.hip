@@ -79,6 +79,30 @@ __device__ __forceinline__ s4 lds_frag(const uint16_t *p)
     return r;
 }
 
+// wavefront max of non-negative ints and sum of floats on DPP row moves
+// (no LDS); the result is taken from the last lane
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
+{
+    uint32_t w;
+    w = dpp_move<0x111, 0xF>(v); v = w > v ? w : v;
+    w = dpp_move<0x112, 0xF>(v); v = w > v ? w : v;
+    w = dpp_move<0x114, 0xF>(v); v = w > v ? w : v;
+    w = dpp_move<0x118, 0xF>(v); v = w > v ? w : v;
+    w = dpp_move<0x142, 0xA>(v); v = w > v ? w : v;
+    w = dpp_move<0x143, 0xC>(v); v = w > v ? w : v;
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+__device__ __forceinline__ float wave_sum_f32(float v)
+{
+    v += __uint_as_float(dpp_move<0x111, 0xF>(__float_as_uint(v)));
+    v += __uint_as_float(dpp_move<0x112, 0xF>(__float_as_uint(v)));
+    v += __uint_as_float(dpp_move<0x114, 0xF>(__float_as_uint(v)));
+    v += __uint_as_float(dpp_move<0x118, 0xF>(__float_as_uint(v)));
+    v += __uint_as_float(dpp_move<0x142, 0xA>(__float_as_uint(v)));
+    v += __uint_as_float(dpp_move<0x143, 0xC>(__float_as_uint(v)));
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 __device__ __forceinline__ f4 mfma(s4 a, s4 b, f4 c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
@@ -224,11 +248,9 @@ __global__ __launch_bounds__(64 * kFwdWaves) void cnn_fwd_kernel(FwdArgs A)
                     best = key > best ? key : best;
                 }
             }
-#pragma unroll
-            for (int o = 32; o >= 1; o >>= 1) {
-                const int other = __shfl_xor(best, o, 64);
-                best = other > best ? other : best;
-            }
+            // every key is positive (the cell has a post), so the zeros the
+            // row moves shift in never win
+            best = (int)wave_max_u32((uint32_t)(best < 0 ? 0 : best));
             const int e = 4095 - (best & 4095);
             const int r = e / A.stride, c = e - r * A.stride;
             cy = li * A.stride + r;
@@ -331,8 +353,11 @@ __global__ __launch_bounds__(64 * kFwdWaves) void cnn_fwd_kernel(FwdArgs A)
                 c3[1] = mfma(a, bw3[tap][1], c3[1]);
             }
         }
-        // ---- ReLU, global average pool over the 9 positions, FC
-        float y = 0.f;
+        // ---- ReLU, global average pool over the 9 positions, FC: each
+        // lane's share of the FC sum over its channels and positions, then
+        // one wavefront sum (the same order in both modes); training also
+        // keeps the pooled features
+        float part = 0.f;
 #pragma unroll
         for (int nt = 0; nt < 2; nt++) {
             float s = 0.f;
@@ -346,19 +371,15 @@ __global__ __launch_bounds__(64 * kFwdWaves) void cnn_fwd_kernel(FwdArgs A)
                         A.H3st[(pid * 9 + pos) * 32 + nt * 16 + lo] = h;
                 }
             }
-            s += __shfl_xor(s, 16, 64);
-            s += __shfl_xor(s, 32, 64);
-            const float g = s / 9.0f;
-            if (kTrain && hi == 0)
-                A.gst[pid * 32 + nt * 16 + lo] = g;
-            y += wfc[nt] * g;
+            part += wfc[nt] * (s / 9.0f);
+            if (kTrain) {
+                float gs = s + __shfl_xor(s, 16, 64);
+                gs += __shfl_xor(gs, 32, 64);
+                if (hi == 0)
+                    A.gst[pid * 32 + nt * 16 + lo] = gs / 9.0f;
+            }
         }
-        // sum over the 16 channels of the lane group (all groups agree)
-        y += __shfl_xor(y, 1, 64);
-        y += __shfl_xor(y, 2, 64);
-        y += __shfl_xor(y, 4, 64);
-        y += __shfl_xor(y, 8, 64);
-        y += bfc;
+        const float y = wave_sum_f32(part) + bfc;
         if (lane == 0) {
             if (kTrain)
                 A.yst[pid] = y;
