@@ -155,7 +155,11 @@ __global__ __launch_bounds__(64 * kFwdWaves) void cnn_fwd_kernel(FwdArgs A)
             bw3[t][nt] = pack4(u[0], u[1], u[2], u[3]);
         }
     }
-    const float b1 = p[OB1 + lo], b2 = p[OB2 + lo];
+    const float b2 = p[OB2 + lo];
+    // conv1 runs transposed (channels x positions): a lane holds channels
+    // 4hi..4hi+3 of one position
+    const float b1q[4] = {p[OB1 + 4 * hi], p[OB1 + 4 * hi + 1], p[OB1 + 4 * hi + 2],
+                          p[OB1 + 4 * hi + 3]};
     const float b3[2] = {p[OB3 + lo], p[OB3 + 16 + lo]};
     const float wfc[2] = {p[OWFC + lo], p[OWFC + 16 + lo]};
     const float bfc = p[OBFC];
@@ -290,14 +294,20 @@ __global__ __launch_bounds__(64 * kFwdWaves) void cnn_fwd_kernel(FwdArgs A)
                 ps[0] = (uint16_t)a.x; ps[1] = (uint16_t)a.y;
                 ps[2] = (uint16_t)a.z; ps[3] = (uint16_t)a.w;
             }
-            f4 c = mfma(a, bw1, f4{0.f, 0.f, 0.f, 0.f});
-#pragma unroll
-            for (int i = 0; i < 4; i++) {
-                const int ox = 4 * hi + i;
-                const uint16_t h = (uint16_t)bf16_bits(fmaxf(c[i] + b1, 0.f));
-                H1[(oy * 16 + ox) * kPosPitch + lo] = h;
-                if (kTrain)
-                    A.H1st[(pid * 256 + oy * 16 + ox) * 16 + lo] = h;
+            // transposed: weights as the row operand, the patch fragment as
+            // the column operand (the same registers); the lane gets
+            // channels 4hi..4hi+3 of position (oy, lo), written as 8 bytes
+            f4 c = mfma(bw1, a, f4{0.f, 0.f, 0.f, 0.f});
+            const s4 h = pack4(fmaxf(c[0] + b1q[0], 0.f), fmaxf(c[1] + b1q[1], 0.f),
+                               fmaxf(c[2] + b1q[2], 0.f), fmaxf(c[3] + b1q[3], 0.f));
+            const int pos = oy * 16 + lo;
+            uint32_t *hw = reinterpret_cast<uint32_t *>(H1 + pos * kPosPitch + 4 * hi);
+            hw[0] = (uint32_t)(uint16_t)h.x | ((uint32_t)(uint16_t)h.y << 16);
+            hw[1] = (uint32_t)(uint16_t)h.z | ((uint32_t)(uint16_t)h.w << 16);
+            if (kTrain) {
+                uint16_t *hs = A.H1st + (pid * 256 + pos) * 16 + 4 * hi;
+                hs[0] = (uint16_t)h.x; hs[1] = (uint16_t)h.y;
+                hs[2] = (uint16_t)h.z; hs[3] = (uint16_t)h.w;
             }
         }
         wave_lds_sync();
