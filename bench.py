@@ -129,6 +129,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the viewshed schedule with the autotuner before timing")
+    ap.add_argument("--schedule-cache", default=None,
+                    help="with --autotune: JSON file of tuned schedules to reuse and extend")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy (counter calibration for rocprof)")
     ap.add_argument("--surrogate-stride", type=int, default=8,
@@ -169,8 +171,14 @@ def main():
         obs_d = S.observers_to_device(res0.observers)
         off_d = torch.from_numpy(res0.offsets).to(dev)
         bm = torch.empty(int(res0.offsets[-1]), dtype=torch.int64, device=dev)
-        sched, times = S.siting_autotune(z, obs_d, off_d, cfg.roi, bm)
-        log(f"[bench] autotuned schedule {sched}: {['%.2f' % t for t in times]} ms")
+        if args.schedule_cache:
+            from paper_2006_16783_amd import schedule_cache
+            sched, hit = schedule_cache.autotune_cached(z, obs_d, off_d, cfg.roi, bm,
+                                                        args.schedule_cache)
+            log(f"[bench] schedule {sched} ({'cached' if hit else 'autotuned, stored'})")
+        else:
+            sched, times = S.siting_autotune(z, obs_d, off_d, cfg.roi, bm)
+            log(f"[bench] autotuned schedule {sched}: {['%.2f' % t for t in times]} ms")
         del bm
 
     for i in range(args.warmup):

@@ -92,3 +92,35 @@ def test_autotune_candidates_bit_identical_contract():
     big = S.siting_autotune_candidates(400)
     assert all(0 <= s.stage_rmax <= 400 for s in big)
     assert any(0 < s.stage_rmax < 400 for s in big)
+
+
+def test_schedule_cache_round_trip(tmp_path):
+    # host logic of the JSON schedule cache, with a stand-in tuner (no GPU)
+    import torch
+    from paper_2006_16783_amd import schedule_cache as SC
+    from paper_2006_16783_amd import Schedule
+    calls = []
+
+    def tune(z, obs, off, rmax, bm, order_dev=None):
+        calls.append(rmax)
+        s = Schedule()
+        s.waves, s.groups_per_cu, s.stage_rmax = 8, 3, rmax
+        return s, [1.5, 2.5]
+
+    z = torch.zeros((300, 200), dtype=torch.int16)
+    obs = torch.zeros((100, 5), dtype=torch.int32)
+    path = str(tmp_path / "sched" / "cache.json")
+    s1, hit1 = SC.autotune_cached(z, obs, None, 90, None, path, tune=tune)
+    s2, hit2 = SC.autotune_cached(z, obs, None, 90, None, path, tune=tune)
+    assert (hit1, hit2) == (False, True) and calls == [90]
+    assert s1.as_tuple() == s2.as_tuple() == (8, 3, 90)
+    # another batch bucket or ROI maximum is tuned again
+    SC.autotune_cached(z, torch.zeros((300, 5), dtype=torch.int32), None, 90, None, path, tune=tune)
+    SC.autotune_cached(z, obs, None, 120, None, path, tune=tune)
+    assert calls == [90, 90, 120]
+    assert len(SC.load(path)) == 3
+    # 100 and 128 observers share a bucket; a corrupt file reads as empty
+    assert SC.cache_key("d", 90, 100, 1, 1) == SC.cache_key("d", 90, 128, 1, 1)
+    assert SC.cache_key("d", 90, 129, 1, 1) != SC.cache_key("d", 90, 128, 1, 1)
+    open(path, "w").write("{not json")
+    assert SC.load(path) == {}
