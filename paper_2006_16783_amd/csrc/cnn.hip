@@ -140,10 +140,14 @@ __global__ __launch_bounds__(64 * kFwdWaves) void cnn_fwd_kernel(FwdArgs A)
     uint16_t *H2 = H1 + 256 * kPosPitch;
     int16_t *tile = reinterpret_cast<int16_t *>(smem + kFwdWaves * kWaveLdsElems * 2);
 
-    // weights as B fragments (bf16) and per-lane biases
+    // weights as B fragments (bf16) and per-lane biases.  Scoring moves the
+    // input's 2^-8 scale into w1: a power-of-two factor commutes with bf16
+    // rounding and with the exact products, so the accumulators are the same
+    // bits (training keeps the scaled patch, which its backward pass reads).
     const float *p = A.params;
-    s4 bw1 = pack4(p[OW1 + lo * 16 + hi * 4 + 0], p[OW1 + lo * 16 + hi * 4 + 1],
-                   p[OW1 + lo * 16 + hi * 4 + 2], p[OW1 + lo * 16 + hi * 4 + 3]);
+    const float w1s = kTrain ? 1.0f : 0.00390625f;
+    s4 bw1 = pack4(p[OW1 + lo * 16 + hi * 4 + 0] * w1s, p[OW1 + lo * 16 + hi * 4 + 1] * w1s,
+                   p[OW1 + lo * 16 + hi * 4 + 2] * w1s, p[OW1 + lo * 16 + hi * 4 + 3] * w1s);
     s4 bw2[9], bw3[9][2];
 #pragma unroll
     for (int t = 0; t < 9; t++) {
@@ -169,8 +173,10 @@ __global__ __launch_bounds__(64 * kFwdWaves) void cnn_fwd_kernel(FwdArgs A)
     int tp = kPatch;               // tile row pitch (a multiple of 4 posts)
     int64_t ty0 = 0, tx0 = 0;      // global post of tile (0,0) (unclamped)
     int nloc = 1;                  // posts handled by this workgroup
+    int64_t bi = 0, bj = 0;        // this workgroup's block of cells
     if (!kTrain) {
-        const int64_t bi = blockIdx.x / A.blocks_c, bj = blockIdx.x % A.blocks_c;
+        bi = blockIdx.x / A.blocks_c;
+        bj = blockIdx.x - bi * A.blocks_c;
         // patches are centred on the highest post of each cell: up to
         // stride-1 posts past the cell corner
         tw = th = A.BL * A.stride + kPatch - 1;
@@ -233,8 +239,8 @@ __global__ __launch_bounds__(64 * kFwdWaves) void cnn_fwd_kernel(FwdArgs A)
             }
             wave_lds_sync();
         } else {
-            const int py = (int)(w / A.BL), px = (int)(w % A.BL);
-            const int64_t bi = blockIdx.x / A.blocks_c, bj = blockIdx.x % A.blocks_c;
+            const int wi = (int)w;  // < BL * BL
+            const int py = wi / A.BL, px = wi - py * A.BL;
             const int64_t li = bi * A.BL + py, lj = bj * A.BL + px;
             if (li >= A.lat_r || lj >= A.lat_c)
                 continue;
@@ -283,7 +289,7 @@ __global__ __launch_bounds__(64 * kFwdWaves) void cnn_fwd_kernel(FwdArgs A)
                 p23 = __builtin_amdgcn_alignbyte(d2, d1, 2);
             }
             // elevation differences in units of 256 m (exact power-of-two scale)
-            constexpr float kScale = 0.00390625f;
+            constexpr float kScale = kTrain ? 0.00390625f : 1.0f;
             const float v0 = (float)((int)(int16_t)(p01 & 0xFFFFu) - zc) * kScale;
             const float v1 = (float)((int)(int16_t)(p01 >> 16) - zc) * kScale;
             const float v2 = (float)((int)(int16_t)(p23 & 0xFFFFu) - zc) * kScale;
