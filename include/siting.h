@@ -64,8 +64,9 @@ typedef struct {
     int32_t waves;          /* wavefronts (64 lanes) per workgroup: 1..16 */
     int32_t groups_per_cu;  /* resident workgroups per compute unit: 1..16 */
     int32_t stage_rmax;     /* observers with roi <= stage_rmax stage their
-                               terrain quadrant in LDS; larger ones read the
-                               terrain through the cache hierarchy. 0 = none */
+                               terrain in LDS (one half-window at a time);
+                               larger ones read the terrain through the cache
+                               hierarchy. 0 = none */
     int32_t reserved;       /* must be 0 */
 } siting_schedule;
 
@@ -223,11 +224,13 @@ int siting_autotune_candidates(int32_t rmax, siting_schedule *out_host, int32_t 
  * when the best gain is 0.  Evaluated lazily with the stage's stated bound
  * (a gain can only shrink as C grows, so a stale gain is an upper bound):
  * the top candidate is taken only once its gain is fresh, which makes the
- * selection exactly the plain greedy one; stale tops are re-evaluated 16 at
- * a time.
+ * selection exactly the plain greedy one; a stale top is re-evaluated and
+ * taken at once if it still beats every other key.
  *   bitmaps/offsets/obs : as produced by siting_viewshed_batch (device)
- *   n < 2^32-1; windows must be those of the same nrows x ncols terrain; a
- *   record with a position or roi out of range counts as gaining nothing
+ *   n: 1 .. about 2.6 million (the block maxima of the keys, 32 bytes per 512
+ *   candidates, live in LDS; SITING_E_UNSUPPORTED beyond); windows must be
+ *   those of the same nrows x ncols terrain; a record with a position or roi
+ *   out of range counts as gaining nothing
  *   cumulative : out (device) uint64[nrows * ceil(ncols/64)], overwritten
  *   selected, gains : out (device) int64[max_obs]; entries past *nselected
  *                     are left untouched
