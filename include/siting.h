@@ -225,10 +225,12 @@ int siting_autotune_candidates(int32_t rmax, siting_schedule *out_host, int32_t 
  * (a gain can only shrink as C grows, so a stale gain is an upper bound):
  * the top candidate is taken only once its gain is fresh, which makes the
  * selection exactly the plain greedy one; a stale top is re-evaluated and
- * taken at once if it still beats every other key.
+ * taken at once if it still beats every other key.  One wavefront runs the
+ * rounds; when some window exceeds 1024 words, three more join the rounds
+ * whose window does (the selection is the same either way).
  *   bitmaps/offsets/obs : as produced by siting_viewshed_batch (device)
- *   n: 1 .. about 2.6 million (the block maxima of the keys, 32 bytes per 512
- *   candidates, live in LDS; SITING_E_UNSUPPORTED beyond); windows must be
+ *   n: 1 .. 4,194,304 (the maxima of the keys over blocks of 512 candidates,
+ *   12 bytes per block, live in LDS; SITING_E_UNSUPPORTED beyond); windows must be
  *   those of the same nrows x ncols terrain; a record with a position or roi
  *   out of range counts as gaining nothing
  *   cumulative : out (device) uint64[nrows * ceil(ncols/64)], overwritten

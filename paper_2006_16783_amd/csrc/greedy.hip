@@ -20,6 +20,14 @@
 // back and the next round pops the new top: each round either selects an
 // observer or lowers a key, and a fresh top (re-evaluated since the last
 // selection) is exact and taken without loading its gain again.
+//
+// Windows above one batch (1024 words: ROI above about 125) make a round
+// latency-bound on one wavefront's loads, so when the largest window exceeds a
+// batch a second instantiation runs instead: wavefront 0 still runs every
+// round alone, and three more wavefronts, waiting at a barrier, join a round
+// whose window is large, each counting (and ORing) every fourth batch.  The
+// host launches both; the largest window, found while the block maxima are
+// built, decides which one returns at once.
 #include <algorithm>
 
 #include "common.hpp"
@@ -31,6 +39,10 @@ constexpr int kGreedyBlock = 512;    // candidates per bmax entry
 constexpr int kGreedyKeys = kGreedyBlock / 64;  // keys of a block per lane
 constexpr int kGreedyWords = 16;     // window words per lane per batch
 constexpr int kGreedyMaxBlocks = 8192;
+#ifndef GREEDY_WAVES
+#define GREEDY_WAVES 4
+#endif
+constexpr int kGreedyWaves = GREEDY_WAVES;  // wavefronts for windows above one batch
 
 // popcount totals of a window: at most (2*16383+1)^2 < 2^31 bits
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) { return wave_sum_u32((uint32_t)v); }
@@ -53,8 +65,10 @@ __device__ __forceinline__ Win window_of(const siting_observer &o, int64_t nrows
     return w;
 }
 
-__global__ void greedy_zero(uint64_t *__restrict__ c, int64_t words)
+__global__ void greedy_zero(uint64_t *__restrict__ c, int64_t words, uint32_t *__restrict__ maxwords)
 {
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        *maxwords = 0;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < words; e += stride)
         c[e] = 0;
@@ -130,43 +144,275 @@ __device__ __forceinline__ void wave_block_max(const uint64_t *key, const int32_
     bfr = __builtin_amdgcn_readlane(f, owner ? __ffsll((long long)owner) - 1 : 0);
 }
 
-// block maxima of the initial keys, one wavefront per block
+// block maxima of the initial keys, one wavefront per block, and the largest
+// window (in words) of any valid candidate
 __global__ __launch_bounds__(64) void greedy_blocks(const uint64_t *__restrict__ key,
-                                                    const int32_t *__restrict__ fresh, int64_t n,
+                                                    const int32_t *__restrict__ fresh,
+                                                    const siting_observer *__restrict__ obs,
+                                                    int64_t n, int64_t nrows, int64_t ncols,
                                                     uint64_t *__restrict__ bmax_g,
-                                                    int32_t *__restrict__ bfr_g)
+                                                    int32_t *__restrict__ bfr_g,
+                                                    uint32_t *__restrict__ maxwords)
 {
     const int b = blockIdx.x, lane = threadIdx.x;
     uint64_t v;
     int32_t f;
     wave_block_max(key, fresh, n, b, lane, -1, 0, 0, v, f);
+    uint32_t mw = 0;
+    for (int u = 0; u < kGreedyKeys; u++) {
+        const int64_t j = (int64_t)b * kGreedyBlock + u * 64 + lane;
+        if (j < n) {
+            const siting_observer o = obs[j];
+            if (obs_ok(o, nrows, ncols)) {
+                const Win w = window_of(o, nrows, ncols);
+                mw = max(mw, (uint32_t)(w.rows * w.nw));
+            }
+        }
+    }
+    mw = (uint32_t)wave_max_u64(mw);
     if (lane == 0) {
         bmax_g[b] = v;
         bfr_g[b] = f;
+        atomicMax(maxwords, mw);
     }
 }
 
-__global__ __launch_bounds__(64) void greedy_run(
+// One wavefront's share of a window: words e = eb + k*estep + 64u + lane
+// (k = 0, 1, ..., u < kGreedyWords), row-major over the window's rows x nw
+// words; the first batch (k = 0) is kept in registers for the OR.
+constexpr int kBatch = 64 * kGreedyWords;
+
+struct Share {
+    const uint64_t *v;  // the candidate's window bitmap
+    int64_t ylo, w0;    // its first row and first word column in C
+    int nw, words;
+    int eb, estep;
+};
+
+// popcount(V & ~C) over the share; `all` = false stops after the first batch,
+// and kTail = false assumes that the window fits the first batch
+template <bool kTail>
+__device__ __forceinline__ uint64_t share_count(const Share &s, const uint64_t *C, int64_t W,
+                                                bool all, int lane, int64_t *cix, uint64_t *vv,
+                                                uint64_t *cc)
+{
+    // the first batch walks the window's rows without division
+    const int nw1 = s.nw > 0 ? s.nw : 1;
+    const int dq = 64 / nw1, dr = 64 - dq * s.nw;
+    {
+        int row = (s.eb + lane) / nw1, col = s.eb + lane - row * s.nw;
+#pragma unroll
+        for (int u = 0; u < kGreedyWords; u++) {
+            cix[u] = (s.ylo + row) * W + s.w0 + col;
+            col += dr;
+            row += dq;
+            if (col >= s.nw) {
+                col -= s.nw;
+                row++;
+            }
+        }
+    }
+    // with tails, a lane past the window's end reads a word that exists (the
+    // window's first, or C's first for an empty window) and keeps zeros, so
+    // that no load sits behind a branch; the single-wavefront kernel keeps
+    // the branches (its compiled schedule is faster with them)
+    if (kTail) {
+        const uint64_t *vsrc = s.words > 0 ? s.v : C;
+#pragma unroll
+        for (int u = 0; u < kGreedyWords; u++) {
+            const bool in = s.eb + u * 64 + lane < s.words;
+            vv[u] = vsrc[in ? s.eb + u * 64 + lane : 0];
+            cc[u] = C[in ? cix[u] : (s.words > 0 ? s.ylo * W + s.w0 : 0)];
+        }
+#pragma unroll
+        for (int u = 0; u < kGreedyWords; u++) {
+            const bool in = s.eb + u * 64 + lane < s.words;
+            vv[u] = in ? vv[u] : 0;
+            cc[u] = in ? cc[u] : 0;
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < kGreedyWords; u++) {
+            const int e = s.eb + u * 64 + lane;
+            vv[u] = 0;
+            cc[u] = 0;
+            if (e < s.words) {
+                vv[u] = s.v[e];
+                cc[u] = C[cix[u]];
+            }
+        }
+    }
+    uint64_t cnt = 0;
+#pragma unroll
+    for (int u = 0; u < kGreedyWords; u++)
+        cnt += __popcll(vv[u] & ~cc[u]);
+    // further batches: positions advance by estep (and by 64 words within a
+    // batch) without division; a lane past the window's end reads its last
+    // word and counts nothing
+    if (kTail && all && s.eb + s.estep < s.words) {
+        const int sq = s.estep / nw1, sr = s.estep - sq * s.nw;
+        int row = (s.eb + lane) / nw1, col = s.eb + lane - row * s.nw;
+        const int last = s.words - 1;
+        const int64_t clast = (s.ylo + last / nw1) * W + s.w0 + (last - (last / nw1) * s.nw);
+        for (int e0 = s.eb + s.estep; e0 < s.words; e0 += s.estep) {
+            col += sr;
+            row += sq;
+            if (col >= s.nw) {
+                col -= s.nw;
+                row++;
+            }
+            uint64_t v2[kGreedyWords], c2[kGreedyWords];
+            int r = row, c = col;
+#pragma unroll
+            for (int u = 0; u < kGreedyWords; u++) {
+                const int e = e0 + u * 64 + lane;
+                const bool in = e < s.words;
+                v2[u] = s.v[in ? e : last];
+                c2[u] = C[in ? (s.ylo + r) * W + s.w0 + c : clast];
+                c += dr;
+                r += dq;
+                if (c >= s.nw) {
+                    c -= s.nw;
+                    r++;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kGreedyWords; u++) {
+                const int e = e0 + u * 64 + lane;
+                cnt += e < s.words ? __popcll(v2[u] & ~c2[u]) : 0;
+            }
+        }
+    }
+    return cnt;
+}
+
+// C |= V over the share (the first batch from registers)
+template <bool kTail>
+__device__ __forceinline__ void share_or(const Share &s, uint64_t *C, int64_t W, int lane,
+                                         const int64_t *cix, const uint64_t *vv,
+                                         const uint64_t *cc)
+{
+#pragma unroll
+    for (int u = 0; u < kGreedyWords; u++) {
+        const int e = s.eb + u * 64 + lane;
+        if (e < s.words)
+            C[cix[u]] = cc[u] | vv[u];
+    }
+    if (!kTail || s.eb + s.estep >= s.words)
+        return;
+    const int nw1 = s.nw > 0 ? s.nw : 1;
+    const int dq = 64 / nw1, dr = 64 - dq * s.nw;
+    const int sq = s.estep / nw1, sr = s.estep - sq * s.nw;
+    int row = (s.eb + lane) / nw1, col = s.eb + lane - row * s.nw;
+    const int last = s.words - 1;
+    const int64_t clast = (s.ylo + last / nw1) * W + s.w0 + (last - (last / nw1) * s.nw);
+    for (int e0 = s.eb + s.estep; e0 < s.words; e0 += s.estep) {
+        col += sr;
+        row += sq;
+        if (col >= s.nw) {
+            col -= s.nw;
+            row++;
+        }
+        uint64_t v2[kGreedyWords], c2[kGreedyWords];
+        int64_t ix[kGreedyWords];
+        int r = row, c = col;
+#pragma unroll
+        for (int u = 0; u < kGreedyWords; u++) {
+            const int e = e0 + u * 64 + lane;
+            const bool in = e < s.words;
+            ix[u] = in ? (s.ylo + r) * W + s.w0 + c : clast;
+            v2[u] = s.v[in ? e : last];
+            c2[u] = C[ix[u]];
+            c += dr;
+            r += dq;
+            if (c >= s.nw) {
+                c -= s.nw;
+                r++;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kGreedyWords; u++) {
+            const int e = e0 + u * 64 + lane;
+            if (e < s.words)
+                C[ix[u]] = c2[u] | v2[u];
+        }
+    }
+}
+
+// What wavefront 0 tells the helper wavefronts about a large window's round.
+struct BigRound {
+    int64_t off, ylo, w0, i;  // off: the window's first word in the bitmaps
+    uint64_t g, second, bo;
+    int nw, words, stale, done;
+};
+
+// The selection loop.  Wavefront 0 runs every round; with kWaves > 1 the
+// other wavefronts wait at a barrier and join only rounds whose window is
+// larger than one batch (64 * kGreedyWords words), each taking every
+// kWaves-th batch, so small windows pay no barrier at all.
+template <int kWaves>
+__global__ __launch_bounds__(64 * kWaves) void greedy_run(
     const uint64_t *__restrict__ bitmaps, const int64_t *__restrict__ offsets,
     const siting_observer *__restrict__ obs, int64_t n, int64_t nrows, int64_t ncols,
     int32_t max_obs, int64_t target, uint64_t *C, int64_t *__restrict__ selected,
     int64_t *__restrict__ gains, int32_t *__restrict__ nselected, uint64_t *key, int32_t *fresh,
-    const uint64_t *__restrict__ bmax_g, const int32_t *__restrict__ bfr_g)
+    const uint64_t *__restrict__ bmax_g, const int32_t *__restrict__ bfr_g,
+    const uint32_t *__restrict__ maxwords)
 {
+    // both instantiations are launched: one wavefront when every window fits
+    // one batch, kWaves otherwise; the other returns at once
+    if ((kWaves > 1) != (*maxwords > (uint32_t)kBatch))
+        return;
     // block maxima of the keys and the round stamps of those maxima
     extern __shared__ uint64_t bmax[];
-    const int lane = threadIdx.x;
+    __shared__ uint32_t s_part[kWaves];
+    __shared__ BigRound s_big;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t W = (ncols + 63) >> 6;
     const int nblocks = (int)((n + kGreedyBlock - 1) / kGreedyBlock);
     int32_t *bfr = reinterpret_cast<int32_t *>(bmax + nblocks);
-    for (int b = lane; b < nblocks; b += 64) {
+    for (int b = threadIdx.x; b < nblocks; b += 64 * kWaves) {
         bmax[b] = bmax_g[b];
         bfr[b] = bfr_g[b];
     }
-    // one wavefront: LDS accesses run in order; the barrier only keeps the
-    // compiler from moving them
     __syncthreads();
 
+    if (kWaves > 1 && wave > 0) {
+        // ---- helper wavefronts: one large-window round per pass
+        for (;;) {
+            __syncthreads();  // wavefront 0 has published the round
+            const BigRound rb = s_big;
+            if (rb.done)
+                break;
+            // the window's address from the kernel argument, so that its loads
+            // stay global loads
+            const Share sh{bitmaps + rb.off, rb.ylo, rb.w0, rb.nw, rb.words, wave * kBatch,
+                           kWaves * kBatch};
+            int64_t cix[kGreedyWords];
+            uint64_t vv[kGreedyWords], cc[kGreedyWords];
+            const uint64_t cnt = share_count<true>(sh, C, W, rb.stale, lane, cix, vv, cc);
+            uint64_t gain = rb.g;
+            if (rb.stale) {
+                const uint32_t part = (uint32_t)wave_sum_u64(cnt);
+                if (lane == 0)
+                    s_part[wave] = part;
+                __syncthreads();  // every share counted
+                uint32_t sum = 0;
+#pragma unroll
+                for (int q = 0; q < kWaves; q++)
+                    sum += s_part[q];
+                gain = sum;
+            }
+            const uint64_t nk = (gain << 32) | (0xFFFFFFFFull - (uint64_t)rb.i);
+            const bool take = gain > 0 && (!rb.stale || (nk > rb.second && nk > rb.bo));
+            if (take)
+                share_or<true>(sh, C, W, lane, cix, vv, cc);
+            __syncthreads();  // every share ORed into C
+        }
+        return;
+    }
+
+    // ---- wavefront 0
     int32_t t = 0;
     int64_t covered = 0;
     // the next round's top is known when a round ends (the larger of the best
@@ -237,71 +483,53 @@ __global__ __launch_bounds__(64) void greedy_run(
             v = bitmaps + off;
         }
         const int words = w.rows * w.nw;
-        // the first batch of window words stays in registers for the OR; the
-        // word index e = 64u + lane walks the window's rows without division
-        const int dq = 64 / (w.nw > 0 ? w.nw : 1), dr = 64 - dq * w.nw;
-        int row0 = lane / (w.nw > 0 ? w.nw : 1), col0 = lane - row0 * w.nw;
+        // the largest key of the top's block other than the top's own (a
+        // large window's round needs it before the helpers start, a small
+        // one after its window loads are in flight)
+        uint64_t bo = 0;
+        int32_t fbo = 0;
+        auto block_other = [&]() {
+            uint64_t kb = 0;
+            int32_t fb = 0;
+#pragma unroll
+            for (int u = 0; u < kGreedyKeys; u++) {
+                if (kk[u] > kb) {
+                    kb = kk[u];
+                    fb = ff[u];
+                }
+            }
+            bo = wave_max_u64(kb);
+            const uint64_t bown = __ballot(kb == bo && bo != 0);
+            fbo = __builtin_amdgcn_readlane(fb, bown ? __ffsll((long long)bown) - 1 : 0);
+        };
+        const bool big = kWaves > 1 && words > kBatch;
+        if (big) {
+            block_other();
+            if (lane == 0)
+                s_big = BigRound{valid ? off : 0, w.ylo, w.w0, i, g, second, bo, w.nw, words,
+                                 stale ? 1 : 0, 0};
+            __syncthreads();  // the helpers start
+        }
+        const Share sh{v, w.ylo, w.w0, w.nw, words, 0, big ? kWaves * kBatch : kBatch};
         int64_t cix[kGreedyWords];
         uint64_t vv[kGreedyWords], cc[kGreedyWords];
-        {
-            int row = row0, col = col0;
+        const uint64_t cnt = share_count<(kWaves > 1)>(sh, C, W, stale, lane, cix, vv, cc);
+        if (!big)
+            block_other();
+        uint64_t gain = g;
+        if (stale) {
+            uint32_t sum = (uint32_t)wave_sum_u64(cnt);
+            if (big) {
+                if (lane == 0)
+                    s_part[0] = sum;
+                __syncthreads();  // every share counted
+                sum = 0;
 #pragma unroll
-            for (int u = 0; u < kGreedyWords; u++) {
-                cix[u] = (w.ylo + row) * W + w.w0 + col;
-                col += dr;
-                row += dq;
-                if (col >= w.nw) {
-                    col -= w.nw;
-                    row++;
-                }
+                for (int q = 0; q < kWaves; q++)
+                    sum += s_part[q];
             }
+            gain = sum;
         }
-#pragma unroll
-        for (int u = 0; u < kGreedyWords; u++) {
-            const int e = u * 64 + lane;
-            vv[u] = 0;
-            cc[u] = 0;
-            if (e < words) {
-                vv[u] = v[e];
-                cc[u] = C[cix[u]];
-            }
-        }
-        uint64_t cnt = 0;
-#pragma unroll
-        for (int u = 0; u < kGreedyWords; u++)
-            cnt += __popcll(vv[u] & ~cc[u]);
-        // windows above 64 * kGreedyWords words: the rest in further batches
-        for (int e0 = 64 * kGreedyWords; stale && e0 < words; e0 += 64 * kGreedyWords) {
-            uint64_t v2[kGreedyWords], c2[kGreedyWords];
-#pragma unroll
-            for (int u = 0; u < kGreedyWords; u++) {
-                const int e = e0 + u * 64 + lane;
-                v2[u] = 0;
-                c2[u] = 0;
-                if (e < words) {
-                    const int row = e / w.nw, c = e - row * w.nw;
-                    v2[u] = v[e];
-                    c2[u] = C[(w.ylo + row) * W + w.w0 + c];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < kGreedyWords; u++)
-                cnt += __popcll(v2[u] & ~c2[u]);
-        }
-        // the largest key of the top's block other than the top's own
-        uint64_t kb = 0;
-        int32_t fb = 0;
-#pragma unroll
-        for (int u = 0; u < kGreedyKeys; u++) {
-            if (kk[u] > kb) {
-                kb = kk[u];
-                fb = ff[u];
-            }
-        }
-        const uint64_t bo = wave_max_u64(kb);
-        const uint64_t bown = __ballot(kb == bo && bo != 0);
-        const int32_t fbo = __builtin_amdgcn_readlane(fb, bown ? __ffsll((long long)bown) - 1 : 0);
-        const uint64_t gain = stale ? wave_sum_u64(cnt) : g;
         const uint64_t nk = (gain << 32) | (0xFFFFFFFFull - (uint64_t)i);
         // lazy greedy: a fresh gain at least every other key (stale or not)
         // is the plain greedy choice; keys are unique
@@ -321,20 +549,12 @@ __global__ __launch_bounds__(64) void greedy_run(
             }
         }
         if (take) {
-#pragma unroll
-            for (int u = 0; u < kGreedyWords; u++) {
-                const int e = u * 64 + lane;
-                if (e < words)
-                    C[cix[u]] = cc[u] | vv[u];
-            }
-            for (int e = 64 * kGreedyWords + lane; e < words; e += 64) {
-                const int row = e / w.nw, c = e - row * w.nw;
-                uint64_t *ce = &C[(w.ylo + row) * W + w.w0 + c];
-                *ce |= v[e];
-            }
+            share_or<(kWaves > 1)>(sh, C, W, lane, cix, vv, cc);
             covered += (int64_t)gain;
             t++;
         }
+        if (big)
+            __syncthreads();  // the helpers' ORs are in C
         // the next top: the best key outside block bi or bi's new maximum
         {
             const uint64_t bnew = ki > bo ? ki : bo;
@@ -356,7 +576,18 @@ __global__ __launch_bounds__(64) void greedy_run(
                 }
             }
         }
-        __syncthreads();
+        // one wavefront's LDS accesses run in order: this only keeps the
+        // compiler from moving them across rounds (with helpers waiting at
+        // the barrier, wavefront 0 alone must not arrive there)
+        if (kWaves == 1)
+            __syncthreads();
+        else
+            __asm__ volatile("" ::: "memory");
+    }
+    if (kWaves > 1) {
+        if (lane == 0)
+            s_big.done = 1;
+        __syncthreads();  // the helpers leave
     }
     if (lane == 0)
         *nselected = t;
@@ -374,7 +605,8 @@ extern "C" size_t siting_greedy_workspace_size(int64_t n)
     if (n < 0)
         return 0;
     const size_t nb = (size_t)((n + kGreedyBlock - 1) / kGreedyBlock);
-    return align256((size_t)n * 8) + align256((size_t)n * 4) + align256(nb * 8) + align256(nb * 4);
+    return align256((size_t)n * 8) + align256((size_t)n * 4) + align256(nb * 8) + align256(nb * 4) +
+           align256(4);
 }
 
 extern "C" int siting_greedy(const uint64_t *bitmaps, const int64_t *offsets,
@@ -397,8 +629,10 @@ extern "C" int siting_greedy(const uint64_t *bitmaps, const int64_t *offsets,
         return SITING_E_WORKSPACE;
     }
     const int64_t nblocks = (n + kGreedyBlock - 1) / kGreedyBlock;
-    if (nblocks > kGreedyMaxBlocks ||
-        nblocks * 12 > kernel_max_dynamic_lds(reinterpret_cast<const void *>(&greedy_run))) {
+    const int lds_max = std::min(
+        kernel_max_dynamic_lds(reinterpret_cast<const void *>(&greedy_run<1>)),
+        kernel_max_dynamic_lds(reinterpret_cast<const void *>(&greedy_run<kGreedyWaves>)));
+    if (nblocks > kGreedyMaxBlocks || nblocks * 12 > lds_max) {
         set_error("%s: %lld candidates exceed the supported maximum", fn, (long long)n);
         return SITING_E_UNSUPPORTED;
     }
@@ -410,24 +644,34 @@ extern "C" int siting_greedy(const uint64_t *bitmaps, const int64_t *offsets,
     uint64_t *bmax_g = reinterpret_cast<uint64_t *>(wsb);
     wsb += align256((size_t)nblocks * 8);
     int32_t *bfr_g = reinterpret_cast<int32_t *>(wsb);
+    wsb += align256((size_t)nblocks * 4);
+    uint32_t *maxwords = reinterpret_cast<uint32_t *>(wsb);
     hipStream_t s = as_stream(stream);
     const int64_t W = (ncols + 63) / 64;
     const int64_t cwords = nrows * W;
     const int zg = (int)std::min<int64_t>((cwords + 255) / 256, (int64_t)device_cus() * 16);
     int rc;
-    hipLaunchKernelGGL(greedy_zero, dim3(zg > 0 ? zg : 1), dim3(256), 0, s, cumulative, cwords);
+    hipLaunchKernelGGL(greedy_zero, dim3(zg > 0 ? zg : 1), dim3(256), 0, s, cumulative, cwords,
+                       maxwords);
     if ((rc = check_launch("greedy_zero")) != SITING_OK)
         return rc;
     hipLaunchKernelGGL(greedy_init, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, bitmaps,
                        offsets, obs, n, nrows, ncols, key, fresh);
     if ((rc = check_launch("greedy_init")) != SITING_OK)
         return rc;
-    hipLaunchKernelGGL(greedy_blocks, dim3((unsigned)nblocks), dim3(64), 0, s, key, fresh, n,
-                       bmax_g, bfr_g);
+    hipLaunchKernelGGL(greedy_blocks, dim3((unsigned)nblocks), dim3(64), 0, s, key, fresh, obs, n,
+                       nrows, ncols, bmax_g, bfr_g, maxwords);
     if ((rc = check_launch("greedy_blocks")) != SITING_OK)
         return rc;
-    hipLaunchKernelGGL(greedy_run, dim3(1), dim3(64), (size_t)nblocks * 12, s, bitmaps, offsets,
+    // one of the two returns at once (the largest window decides)
+    hipLaunchKernelGGL(greedy_run<1>, dim3(1), dim3(64), (size_t)nblocks * 12, s, bitmaps, offsets,
                        obs, n, nrows, ncols, max_obs, target_cells, cumulative, selected, gains,
-                       nselected, key, fresh, bmax_g, bfr_g);
+                       nselected, key, fresh, bmax_g, bfr_g, maxwords);
+    if ((rc = check_launch("greedy_run")) != SITING_OK)
+        return rc;
+    hipLaunchKernelGGL(greedy_run<kGreedyWaves>, dim3(1), dim3(64 * kGreedyWaves),
+                       (size_t)nblocks * 12, s, bitmaps, offsets, obs, n, nrows, ncols, max_obs,
+                       target_cells, cumulative, selected, gains, nselected, key, fresh, bmax_g,
+                       bfr_g, maxwords);
     return check_launch("greedy_run");
 }

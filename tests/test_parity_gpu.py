@@ -217,6 +217,30 @@ def test_greedy_parity(S, orc, seed, n_obs, max_obs, frac, roi):
     assert (_u64(cum).reshape(-1) == wcum.reshape(-1)).all()
 
 
+@pytest.mark.parametrize("seed,n_obs,roi", [
+    (11, 120, (400, 600)),   # every window spans several batches of every wavefront
+    (12, 300, (5, 600)),     # small and large windows interleave
+])
+def test_greedy_large_windows(S, orc, seed, n_obs, roi):
+    # windows above 1024 words run on four wavefronts; same selection as the
+    # oracle's greedy over the oracle's own viewsheds
+    _say("greedy large windows", seed, n_obs, roi)
+    from synth import uniform_observers
+    nr, nc = 1300, 1210
+    z = _terrain(nr, 2.4, 1500, seed, ncols=nc)
+    obs = uniform_observers(nr, nc, n_obs, seed, roi=roi, height=(5, 60))
+    bm_h, off = orc.viewshed(z, obs)
+    wsel, wgain, wcum, _ = orc.greedy(bm_h, off, obs, nr, nc, 150, nr * nc, lazy=True)
+    bm = torch.from_numpy(bm_h.view(np.int64)).cuda()
+    sel, gains, nsel, cum = S.siting_greedy(bm, torch.from_numpy(off).cuda(),
+                                            S.observers_to_device(obs), nr, nc, 150, nr * nc)
+    m = int(nsel.item())
+    assert m == len(wsel)
+    assert (sel[:m].cpu().numpy() == wsel).all()
+    assert (gains[:m].cpu().numpy() == wgain).all()
+    assert (_u64(cum).reshape(-1) == wcum.reshape(-1)).all()
+
+
 # ------------------------------------------------------------- PIPELINE ----
 def test_pipeline_plain_1000_end_to_end(S, orc):
     from paper_2006_16783_amd import pipeline as P
