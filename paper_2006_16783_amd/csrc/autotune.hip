@@ -16,6 +16,7 @@ int viewshed_launch(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
                     hipStream_t s);
 int viewshed_lds_bytes(int32_t rmax, int32_t stage_rmax);
 int viewshed_max_dynamic_lds();
+bool quad_mode(int rmax);
 int validate_schedule(const siting_schedule &sc, const char *fn);
 }  // namespace siting
 
@@ -30,16 +31,25 @@ extern "C" int siting_autotune_candidates(int32_t rmax, siting_schedule *out_hos
     std::vector<siting_schedule> c;
     // stage everything, nothing, or only the observers up to a partial ROI
     // (uneven batches: small observers from LDS, large ones through L2)
-    std::vector<int> stages{rmax, 0};
-    for (int st : {64, 100, 128, 160, 200, 256})
-        if (st < rmax)
-            stages.push_back(st);
+    // (windows too large for an LDS bitmap: quadrant mode, no staging)
+    const bool quad = quad_mode(rmax);
+    std::vector<int> stages{quad ? 0 : rmax};
+    if (!quad) {
+        stages.push_back(0);
+        for (int st : {64, 100, 128, 160, 200, 256})
+            if (st < rmax)
+                stages.push_back(st);
+    }
     for (int stage : stages) {
         int lds = viewshed_lds_bytes(rmax, stage);
         if (lds > budget)
             continue;
         int fit = std::max(1, std::min(16, budget / lds));
-        for (int waves : {2, 4, 8}) {
+        for (int waves : {2, 4, 8, 16}) {
+            // quadrant mode sweeps about 2R rays per quadrant: 8 or 16
+            // wavefronts; otherwise 2 to 8
+            if (quad ? waves < 8 : waves > 8)
+                continue;
             for (int g : {fit, std::max(1, fit / 2)}) {
                 siting_schedule s{waves, g, stage, 0};
                 bool dup = false;

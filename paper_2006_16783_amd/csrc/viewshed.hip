@@ -332,6 +332,17 @@ __host__ __device__ __forceinline__ int bm_bytes(int rmax)
 {
     return (2 * rmax + 1) * bm_pitch_dw(rmax) * 4;
 }
+// Quadrant mode (windows too large for LDS): one quadrant's bitmap at a time,
+// (rmax+1) rows of at most (rmax>>6)+2 words, odd dword pitch.
+__host__ __device__ __forceinline__ int bmq_pitch_dw(int rmax)
+{
+    return 2 * ((rmax >> 6) + 2) + 1;
+}
+__host__ __device__ __forceinline__ int bmq_bytes(int rmax)
+{
+    // plus the count sink's row and column masks (2R+1 bits each)
+    return (rmax + 1) * bmq_pitch_dw(rmax) * 4 + 2 * ((2 * rmax + 1 + 31) >> 5) * 4;
+}
 // A staged half-window (at most rmax+1 rows of 2*rmax+1 posts) keeps the
 // terrain's orientation; its rows start at an even terrain column, so a row
 // spans at most 2*rmax+2 posts, and an odd dword pitch puts a column's posts in
@@ -365,7 +376,7 @@ __global__ void viewshed_kernel(const int16_t *__restrict__ z, int64_t nrows, in
                                 const int32_t *__restrict__ order, int sink,
                                 uint64_t *__restrict__ bitmaps, uint32_t *__restrict__ visible,
                                 uint32_t *__restrict__ cells, uint32_t *queue, int rmax,
-                                int stage_rmax, int dma)
+                                int stage_rmax, int dma, int quad)
 {
     extern __shared__ uint32_t lds[];
     __shared__ int64_t s_task;
@@ -414,6 +425,125 @@ __global__ void viewshed_kernel(const int16_t *__restrict__ z, int64_t nrows, in
         const int R2 = R * R;
         const int16_t *zo = z + y * ld + x;
         const int E = (int)zo[0] + o.h_t;
+
+        if (quad) {
+            // one quadrant at a time in LDS, terrain from global memory; each
+            // quadrant's words go out at once, ORed where an earlier quadrant
+            // wrote the same word (the observer's row and the word holding
+            // its column), so the window is written exactly once over
+            const int QPdw = bmq_pitch_dw(rmax), QP = QPdw * 32;
+            const int64_t xw = x >> 6;
+            uint32_t vis = 0;
+            GlobalSrc src{zo};
+            // count sink: masks of the visible cells on the observer's row
+            // (bit c - xlo) and column (bit r - ylo), after the bitmap
+            const int axdw = (2 * rmax + 1 + 31) >> 5;
+            uint32_t *axr = bm + (rmax + 1) * QPdw, *axc = axr + axdw;
+            if (sink == SITING_SINK_COUNT)
+                for (int e = tid; e < 2 * axdw; e += nthreads)
+                    axr[e] = 0;
+            for (int qd = 0; qd < 4; qd++) {
+                const int64_t row0 = qd < 2 ? y : ylo;
+                const int nrq = qd < 2 ? ey_p + 1 : ey_m + 1;
+                const int64_t c0 = (qd == 0 || qd == 3) ? x : xlo;
+                const int64_t c1 = (qd == 0 || qd == 3) ? xhi : x;
+                const int64_t word0 = c0 >> 6;
+                const int nwq = (int)((c1 >> 6) - word0 + 1);
+                const int P0q = (int)(y - row0) * QP + (int)(x - (word0 << 6));
+                for (int e = tid; e < nrq * QPdw; e += nthreads)
+                    bm[e] = 0;
+                __syncthreads();
+                if (tid == 0)
+                    atomicOr(&bm[P0q >> 5], 1u << (P0q & 31));
+                const Quadrant Q = make_quadrant(qd, ex_p, ex_m, ey_p, ey_m, QP, (int)ld);
+                const int nrays = Q.eu >= 1 ? Q.eu + Q.ev : 0;
+                for (int rho = tid; rho < nrays; rho += nthreads) {
+                    int du, dv;
+                    ray_target(Q, rho, du, dv);
+                    sweep<false, true>(src, Q.gu, Q.gv, bm, P0q, Q.bu, Q.bv, du, dv, R2, E,
+                                       o.h_r);
+                }
+                __syncthreads();
+                if (sink == SITING_SINK_BITMAP) {
+                    uint64_t *out = bitmaps + offsets[i];
+                    for (int e = tid; e < nrq * nwq; e += nthreads) {
+                        const int r = e / nwq, w = e - r * nwq;
+                        const int64_t grow = row0 + r, gw = word0 + w;
+                        const uint32_t *q = bm + r * QPdw + 2 * w;
+                        const uint64_t val = (uint64_t)q[0] | ((uint64_t)q[1] << 32);
+                        uint64_t *dst = out + (grow - ylo) * nw + (gw - w0);
+                        const bool shared = (qd == 1 && gw == xw) || (qd == 2 && grow == y) ||
+                                            (qd == 3 && (grow == y || gw == xw));
+                        if (shared)
+                            *dst |= val;
+                        else
+                            *dst = val;
+                    }
+                } else {
+                    // count each cell once: the observer's row and column,
+                    // which two quadrants share, are ORed into the axis masks
+                    // and cleared here; the rest is this quadrant's alone
+                    const int xb = (int)(x - (word0 << 6)), ry = (int)(y - row0);
+                    for (int64_t c = c0 + tid; c <= c1; c += nthreads) {
+                        const int b = ry * QP + (int)(c - (word0 << 6));
+                        if ((bm[b >> 5] >> (b & 31)) & 1u)
+                            atomicOr(&axr[(c - xlo) >> 5], 1u << ((c - xlo) & 31));
+                    }
+                    for (int r = tid; r < nrq; r += nthreads) {
+                        const int b = r * QP + xb;
+                        const int64_t gr = row0 + r - ylo;
+                        if ((bm[b >> 5] >> (b & 31)) & 1u)
+                            atomicOr(&axc[gr >> 5], 1u << (gr & 31));
+                    }
+                    __syncthreads();
+                    for (int r = tid; r < nrq; r += nthreads)
+                        bm[r * QPdw + (xb >> 5)] &= ~(1u << (xb & 31));
+                    __syncthreads();
+                    for (int e = tid; e < QPdw; e += nthreads)
+                        bm[ry * QPdw + e] = 0;
+                    __syncthreads();
+                    for (int e = tid; e < nrq * QPdw; e += nthreads)
+                        vis += __popc(bm[e]);
+                }
+                __syncthreads();
+            }
+            if (sink == SITING_SINK_COUNT) {
+                // the axes: row y from the row mask, column x (without the
+                // observer's own cell, already in the row) from the column mask
+                const int yb = (int)(y - ylo);
+                for (int e = tid; e < axdw; e += nthreads) {
+                    const uint32_t cm = e == (yb >> 5) ? axc[e] & ~(1u << (yb & 31)) : axc[e];
+                    vis += __popc(axr[e]) + __popc(cm);
+                }
+                uint32_t cnt = 0;
+                for (int row = tid; row < rows; row += nthreads) {
+                    int dy = (int)(ylo + row - y);
+                    int hw = isqrt_floor(R2 - dy * dy);
+                    int64_t a = x - hw < xlo ? xlo : x - hw;
+                    int64_t b = x + hw > xhi ? xhi : x + hw;
+                    if (b >= a)
+                        cnt += (uint32_t)(b - a + 1);
+                }
+                vis = wave_sum_u32(vis);
+                cnt = wave_sum_u32(cnt);
+                if (lane == 0) {
+                    s_sum[wave] = vis;
+                    s_sum[16 + wave] = cnt;
+                }
+                __syncthreads();
+                if (tid == 0) {
+                    uint32_t tv = 0, tc = 0;
+                    for (int w = 0; w < nwaves; w++) {
+                        tv += s_sum[w];
+                        tc += s_sum[16 + w];
+                    }
+                    visible[i] = tv;
+                    cells[i] = tc;
+                }
+            }
+            __syncthreads();
+            continue;
+        }
 
         for (int e = tid; e < rows * BPdw; e += nthreads)
             bm[e] = 0;
@@ -612,11 +742,6 @@ __global__ void viewshed_kernel(const int16_t *__restrict__ z, int64_t nrows, in
     }
 }
 
-int lds_bytes_for(int rmax, int stage_rmax)
-{
-    return bm_bytes(rmax) + zq_bytes(std::min(stage_rmax, rmax));
-}
-
 }  // namespace
 
 int viewshed_max_dynamic_lds()
@@ -624,13 +749,26 @@ int viewshed_max_dynamic_lds()
     return kernel_max_dynamic_lds(reinterpret_cast<const void *>(&viewshed_kernel));
 }
 
+// Windows whose bitmap exceeds LDS run in quadrant mode (terrain from global
+// memory, staging off).
+bool quad_mode(int rmax) { return bm_bytes(rmax) > viewshed_max_dynamic_lds(); }
+
+int lds_bytes_for(int rmax, int stage_rmax)
+{
+    if (quad_mode(rmax))
+        return bmq_bytes(rmax);
+    return bm_bytes(rmax) + zq_bytes(std::min(stage_rmax, rmax));
+}
+
+
 int viewshed_launch(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
                     const siting_observer *obs, int64_t n, const int64_t *offsets,
                     const int32_t *order, int32_t rmax, const siting_schedule &sc, int32_t sink,
                     uint64_t *bitmaps, uint32_t *visible, uint32_t *cells, void *ws,
                     hipStream_t s)
 {
-    int stage = std::min(sc.stage_rmax, rmax);
+    const int quad = quad_mode(rmax) ? 1 : 0;
+    int stage = quad ? 0 : std::min(sc.stage_rmax, rmax);
     int lds = lds_bytes_for(rmax, stage);
     if (lds > viewshed_max_dynamic_lds()) {
         set_error("siting_viewshed_batch: schedule needs %d bytes of LDS (at most %d)", lds,
@@ -651,7 +789,7 @@ int viewshed_launch(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
     const int dma = ld % 2 == 0 && ncols % 2 == 0 && reinterpret_cast<uintptr_t>(z) % 4 == 0;
     hipLaunchKernelGGL(viewshed_kernel, dim3((unsigned)grid), dim3(64 * sc.waves), (size_t)lds, s,
                        z, nrows, ncols, ld, obs, n, offsets, order, sink, bitmaps, visible, cells,
-                       queue, rmax, stage, dma);
+                       queue, rmax, stage, dma, quad);
     return check_launch("viewshed_kernel");
 }
 
@@ -666,6 +804,12 @@ int viewshed_default_schedule(int32_t rmax, siting_schedule *sc)
         sc->waves = std::max(2, std::min(8, (4 * rmax + 63) / 64 + 1));
         sc->stage_rmax = rmax;
         sc->groups_per_cu = std::max(1, std::min(8, budget / lds_staged));
+    } else if (quad_mode(rmax)) {
+        // one workgroup per CU holds a quadrant's bitmap; its 2R rays fill
+        // 16 wavefronts about twice
+        sc->stage_rmax = 0;
+        sc->waves = 16;
+        sc->groups_per_cu = 1;
     } else {
         sc->stage_rmax = 0;
         sc->waves = 8;

@@ -143,6 +143,36 @@ def test_viewshed_strided_terrain(S, orc, ld):
     assert (_u64(bm)[:off[-1]] == want).all()
 
 
+def _quadrant_observers(nr, nc, n, seed, roi, height):
+    # uniform posts plus the four corners and the four edge midpoints
+    from synth import uniform_observers
+    obs = uniform_observers(nr, nc, n, seed, roi=roi, height=height)
+    ex = np.zeros(8, obs.dtype)
+    ex["x"] = [0, nc - 1, 0, nc - 1, nc // 2, nc // 2, 0, nc - 1]
+    ex["y"] = [0, 0, nr - 1, nr - 1, 0, nr - 1, nr // 2, nr // 2]
+    ex["roi"], ex["h_t"], ex["h_r"] = roi[1], height[1], height[0]
+    return np.concatenate([obs, ex])
+
+
+@pytest.mark.parametrize("seed,roi,shape", [
+    (31, (560, 800), (1300, 1250)),   # every window in quadrant mode
+    (32, (5, 700), (1100, 1170)),     # small and large ROIs in one quadrant-mode batch
+])
+def test_viewshed_quadrant_mode(S, orc, seed, roi, shape):
+    # windows whose bitmap exceeds LDS: one quadrant at a time, both sinks
+    _say("viewshed quadrant mode", seed, roi, shape)
+    nr, nc = shape
+    z = _terrain(nr, 2.4, 2500, seed, ncols=nc)
+    obs = _quadrant_observers(nr, nc, 40, seed, roi, (0, 60))
+    got, want = _viewshed_case(S, orc, z, obs, roi[1])
+    assert (got == want).all()
+    vis, cells = S.siting_viewshed_batch(torch.from_numpy(z).cuda(), S.observers_to_device(obs),
+                                         None, roi[1], sink=S.SITING_SINK_COUNT)
+    wv, wc = orc.viewshed_count(z, obs)
+    assert (vis.cpu().numpy().astype(np.uint32) == wv).all()
+    assert (cells.cpu().numpy().astype(np.uint32) == wc).all()
+
+
 def test_viewshed_every_schedule_same_bits(S, orc):
     from synth import uniform_observers
     z = _terrain(500, 2.4, 2000, 8)
