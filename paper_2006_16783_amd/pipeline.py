@@ -50,6 +50,16 @@ CONFIGS = {
     # 46400^2 (2.15e9 posts), ROI 100, 64x64 blocks x 20, SITE to 4096
     "full_46400": SitingConfig("full_46400", 46400, 2.4, 4000, 1, 100, 10, 10, 10, 64, 20,
                                4096, 1.0),
+    # the paper's billion-post runs (Tables 2 and 3) as synthetic stand-ins:
+    # its terrain sizes and elevation spans, h_t = 100, h_r = 10, blocks of
+    # side floor(R/3) with 20 candidates each, SITE to the paper's observer
+    # counts
+    "east_32000_r500": SitingConfig("east_32000_r500", 32000, 2.4, 507, 1, 500, 100, 10, 10,
+                                    193, 20, 6543, 1.0),
+    "east_32000_r1000": SitingConfig("east_32000_r1000", 32000, 2.4, 507, 1, 1000, 100, 10, 10,
+                                     96, 20, 5000, 1.0),
+    "west_46400_r1000": SitingConfig("west_46400_r1000", 46400, 2.4, 2706, 1, 1000, 100, 10, 10,
+                                     139, 20, 5647, 1.0),
 }
 
 
@@ -77,19 +87,24 @@ def disk_cell_counts(obs: np.ndarray, nrows: int, ncols: int) -> np.ndarray:
     counted row by row on the host for the throughput metric."""
     out = np.zeros(len(obs), np.int64)
     for R in np.unique(obs["roi"]):
-        sel = np.nonzero(obs["roi"] == R)[0]
+        R = int(R)
+        sel_all = np.nonzero(obs["roi"] == R)[0]
         dy = np.arange(-R, R + 1)
         half = np.floor(np.sqrt(np.maximum(R * R - dy * dy, 0))).astype(np.int64)
         # exact integer square root correction
         half -= (half * half > R * R - dy * dy)
         half += ((half + 1) * (half + 1) <= R * R - dy * dy)
-        x = obs["x"][sel].astype(np.int64)[:, None]
-        y = obs["y"][sel].astype(np.int64)[:, None]
-        rows = y + dy[None, :]
-        lo = np.maximum(x - half[None, :], 0)
-        hi = np.minimum(x + half[None, :], ncols - 1)
-        cnt = np.where((rows >= 0) & (rows < nrows), np.maximum(hi - lo + 1, 0), 0)
-        out[sel] = cnt.sum(axis=1)
+        # observers in chunks of about 2^23 row entries
+        step = max(1, (1 << 23) // (2 * R + 1))
+        for c0 in range(0, len(sel_all), step):
+            sel = sel_all[c0:c0 + step]
+            x = obs["x"][sel].astype(np.int64)[:, None]
+            y = obs["y"][sel].astype(np.int64)[:, None]
+            rows = y + dy[None, :]
+            lo = np.maximum(x - half[None, :], 0)
+            hi = np.minimum(x + half[None, :], ncols - 1)
+            cnt = np.where((rows >= 0) & (rows < nrows), np.maximum(hi - lo + 1, 0), 0)
+            out[sel] = cnt.sum(axis=1)
     return out
 
 
@@ -99,22 +114,34 @@ _QUAD_STEPS: dict = {}
 def _quadrant_ray_steps(eu: int, ev: int, R: int) -> int:
     """Ray steps that test a cell in one quadrant of a window (rays to the
     far sides u = eu and v = ev; each ray stops when its nearest cell leaves
-    the ROI disk).  Geometry only, independent of the terrain."""
+    the ROI disk).  Geometry only, independent of the terrain.  Along a ray
+    of n major steps and minor extent mn, step k lands at minor offset
+    m(k) = floor((2*k*mn + n) / (2n)), so k^2 + m(k)^2 grows with k and the
+    ray's steps are the k <= n with k^2 + m(k)^2 <= R^2: the largest such k,
+    found from a float estimate corrected by exact integer tests."""
     key = (eu, ev, R)
     if key in _QUAD_STEPS:
         return _QUAD_STEPS[key]
     if eu < 1:
         _QUAD_STEPS[key] = 0
         return 0
-    rho = np.arange(eu + ev)
+    rho = np.arange(eu + ev, dtype=np.int64)
     du = np.where(rho <= ev, eu, eu - (rho - ev))
     dv = np.where(rho <= ev, rho, ev)
-    n = np.maximum(du, dv).astype(np.int64)
-    mn = np.minimum(du, dv).astype(np.int64)
-    k = np.arange(1, int(n.max()) + 1, dtype=np.int64)[None, :]
-    m = (2 * k * mn[:, None] + n[:, None]) // (2 * n[:, None])
-    ok = (k <= n[:, None]) & (k * k + m * m <= R * R)
-    tot = int(np.cumprod(ok, axis=1).sum())
+    n = np.maximum(du, dv)
+    mn = np.minimum(du, dv)
+
+    def ok(k):
+        m = (2 * k * mn + n) // (2 * n)
+        return (k >= 1) & (k <= n) & (k * k + m * m <= R * R)
+
+    k = np.minimum(n, np.floor(R / np.sqrt(1.0 + (mn / n) ** 2)).astype(np.int64))
+    for _ in range(4):
+        k = np.where(ok(k + 1), k + 1, k)
+    for _ in range(4):
+        k = np.where((k >= 1) & ~ok(k), k - 1, k)
+    assert ok(k).sum() == (k >= 1).sum() and not ok(k + 1).any()
+    tot = int(k.sum())
     _QUAD_STEPS[key] = tot
     return tot
 

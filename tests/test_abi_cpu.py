@@ -124,3 +124,42 @@ def test_schedule_cache_round_trip(tmp_path):
     assert SC.cache_key("d", 90, 129, 1, 1) != SC.cache_key("d", 90, 128, 1, 1)
     open(path, "w").write("{not json")
     assert SC.load(path) == {}
+
+
+def test_ray_step_counts_match_brute_force():
+    # the closed-form per-ray step count against stepping every ray
+    from paper_2006_16783_amd import pipeline as P
+
+    def brute(eu, ev, R):
+        if eu < 1:
+            return 0
+        tot = 0
+        for rho in range(eu + ev):
+            du, dv = (eu, rho) if rho <= ev else (eu - (rho - ev), ev)
+            n, mn = max(du, dv), min(du, dv)
+            for k in range(1, n + 1):
+                m = (2 * k * mn + n) // (2 * n)
+                if k * k + m * m > R * R:
+                    break
+                tot += 1
+        return tot
+
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        R = int(rng.integers(1, 60))
+        eu, ev = int(rng.integers(0, R + 1)), int(rng.integers(0, R + 1))
+        assert P._quadrant_ray_steps(eu, ev, R) == brute(eu, ev, R), (eu, ev, R)
+    for R in (1, 2, 7, 64):
+        assert P._quadrant_ray_steps(R, R, R) == brute(R, R, R)
+
+
+def test_paper_scale_configs():
+    # block grids follow G = round(N / floor(R/3)) (Tables 2 and 3)
+    import oracle
+    from paper_2006_16783_amd import pipeline as P
+    for name, (n, R, G) in {"east_32000_r500": (32000, 500, 193),
+                            "east_32000_r1000": (32000, 1000, 96),
+                            "west_46400_r1000": (46400, 1000, 139)}.items():
+        c = P.CONFIGS[name]
+        assert (c.n, c.roi, c.grid, c.k, c.h_t, c.h_r) == (n, R, G, 20, 100, 10)
+        assert oracle.block_grid(n, R) == G

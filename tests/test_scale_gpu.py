@@ -149,3 +149,63 @@ def test_uneven_16384_autotuned(S, orc):
     _check_site(orc, bm_h, off, obs, n, n, 4000, n * n, sel[:m].cpu().numpy(),
                 gains[:m].cpu().numpy())
     _say("uneven ok", m)
+
+
+def test_paper_roi_east_32000_r1000(S, orc):
+    # the paper's second billion-post run as a synthetic stand-in: 32000^2,
+    # ROI 1000 (quadrant-mode viewsheds), h 100/10, 96x96 blocks x 20 =
+    # 184,320 candidates, SITE to 5000 (four-wavefront rounds)
+    from paper_2006_16783_amd import pipeline as P
+    from synth import fbm_torch
+    cfg = P.CONFIGS["east_32000_r1000"]
+    t0 = time.time()
+    z = fbm_torch(cfg.n, cfg.beta, cfg.zmax, cfg.seed, device="cuda")
+    cnt = S.siting_vix(z, cfg.roi, cfg.h_t, cfg.h_r, cfg.K, cfg.vix_seed)
+    res = P.run(z, cfg, key=cnt)   # the same path, ranked by these counts
+    _say("paper roi pipeline", res.stage_ms, len(res.observers), len(res.selected))
+    assert len(res.observers) == 96 * 96 * 20 and 0 < len(res.selected) <= 5000
+    z_host = z.cpu().numpy()
+    _check_rows(orc, z_host, cnt, cfg, [0, cfg.n // 2, cfg.n - 1])
+    cnt_h = cnt.cpu().numpy()
+    del cnt
+    cand = res.candidates
+    G = cfg.grid
+    _check_blocks(cnt_h, z_host, cand, G, cfg.k, [0, G - 1, G * G - 1, G * (G - 1), 4321])
+    del cnt_h
+    _say("paper roi vix and findmax ok")
+    obs, off = res.observers, res.offsets
+    obs_d = S.observers_to_device(obs)
+    # viewsheds of sampled candidates (edge windows included), swept by the
+    # same quadrant-mode launch on the subset
+    picks = _edge_picks(obs, cfg.n, cfg.n, 24, np.random.default_rng(5))
+    sub = obs[picks]
+    soff = S.siting_viewshed_layout(sub, cfg.n, cfg.n)
+    sbm = S.siting_viewshed_batch(z, S.observers_to_device(sub), torch.from_numpy(soff).cuda(),
+                                  cfg.roi)
+    _check_viewsheds(orc, z_host, sub, soff, _u64(sbm), range(len(sub)))
+    _say("paper roi viewsheds ok")
+    # SITE: the first pick is the largest viewshed (ties to the lowest
+    # index), and replaying the selection over the device bitmaps gives
+    # every recorded gain (popcount of the window outside the union so far)
+    vis, _ = S.siting_viewshed_batch(z, obs_d, None, cfg.roi, sink=S.SITING_SINK_COUNT)
+    vis = vis.cpu().numpy().astype(np.int64)
+    assert res.selected[0] == int(np.argmax(vis)) and res.gains[0] == vis.max()
+    bm = S.siting_viewshed_batch(z, obs_d, torch.from_numpy(off).cuda(), cfg.roi)
+    W = (cfg.n + 63) // 64
+    C = np.zeros((cfg.n, W), np.uint64)
+    for t, i in enumerate(res.selected):
+        o = obs[i]
+        R, x, y = int(o["roi"]), int(o["x"]), int(o["y"])
+        ylo, yhi = max(0, y - R), min(cfg.n - 1, y + R)
+        w0, w1 = max(0, x - R) >> 6, min(cfg.n - 1, x + R) >> 6
+        win = _u64(bm[int(off[i]):int(off[i + 1])]).reshape(yhi - ylo + 1, w1 - w0 + 1)
+        cv = C[ylo:yhi + 1, w0:w1 + 1]
+        g = int(np.bitwise_count(win & ~cv).sum())
+        assert g == res.gains[t], ("site replay", t, i, g, res.gains[t])
+        cv |= win
+    assert (np.diff(res.gains) <= 0).all()
+    _say("paper roi site replay ok", time.time() - t0)
+
+
+def _u64(t):
+    return t.cpu().numpy().view(np.uint64)
