@@ -25,9 +25,10 @@
 // latency-bound on one wavefront's loads, so when the largest window exceeds a
 // batch a second instantiation runs instead: wavefront 0 still runs every
 // round alone, and three more wavefronts, waiting at a barrier, join a round
-// whose window is large, each counting (and ORing) every fourth batch.  The
-// host launches both; the largest window, found while the block maxima are
-// built, decides which one returns at once.
+// whose window is large, each counting (and ORing) every fourth batch with all
+// of a batch's loads in flight (nothing kept in registers between the count and
+// the OR, which reloads).  The host launches both; the largest window, found
+// while the block maxima are built, decides which one returns at once.
 #include <algorithm>
 
 #include "common.hpp"
@@ -177,9 +178,8 @@ __global__ __launch_bounds__(64) void greedy_blocks(const uint64_t *__restrict__
     }
 }
 
-// One wavefront's share of a window: words e = eb + k*estep + 64u + lane
-// (k = 0, 1, ..., u < kGreedyWords), row-major over the window's rows x nw
-// words; the first batch (k = 0) is kept in registers for the OR.
+// A window (or one wavefront's share of it): words e = eb + k*estep + 64u +
+// lane, row-major over the window's rows x nw words.
 constexpr int kBatch = 64 * kGreedyWords;
 
 struct Share {
@@ -189,18 +189,16 @@ struct Share {
     int eb, estep;
 };
 
-// popcount(V & ~C) over the share; `all` = false stops after the first batch,
-// and kTail = false assumes that the window fits the first batch
-template <bool kTail>
+// A window of at most one batch: popcount(V & ~C), the words kept in
+// registers for the OR (row and column stepped without division).
 __device__ __forceinline__ uint64_t share_count(const Share &s, const uint64_t *C, int64_t W,
-                                                bool all, int lane, int64_t *cix, uint64_t *vv,
+                                                int lane, int64_t *cix, uint64_t *vv,
                                                 uint64_t *cc)
 {
-    // the first batch walks the window's rows without division
     const int nw1 = s.nw > 0 ? s.nw : 1;
     const int dq = 64 / nw1, dr = 64 - dq * s.nw;
     {
-        int row = (s.eb + lane) / nw1, col = s.eb + lane - row * s.nw;
+        int row = lane / nw1, col = lane - row * s.nw;
 #pragma unroll
         for (int u = 0; u < kGreedyWords; u++) {
             cix[u] = (s.ylo + row) * W + s.w0 + col;
@@ -212,116 +210,60 @@ __device__ __forceinline__ uint64_t share_count(const Share &s, const uint64_t *
             }
         }
     }
-    // with tails, a lane past the window's end reads a word that exists (the
-    // window's first, or C's first for an empty window) and keeps zeros, so
-    // that no load sits behind a branch; the single-wavefront kernel keeps
-    // the branches (its compiled schedule is faster with them)
-    if (kTail) {
-        const uint64_t *vsrc = s.words > 0 ? s.v : C;
 #pragma unroll
-        for (int u = 0; u < kGreedyWords; u++) {
-            const bool in = s.eb + u * 64 + lane < s.words;
-            vv[u] = vsrc[in ? s.eb + u * 64 + lane : 0];
-            cc[u] = C[in ? cix[u] : (s.words > 0 ? s.ylo * W + s.w0 : 0)];
-        }
-#pragma unroll
-        for (int u = 0; u < kGreedyWords; u++) {
-            const bool in = s.eb + u * 64 + lane < s.words;
-            vv[u] = in ? vv[u] : 0;
-            cc[u] = in ? cc[u] : 0;
-        }
-    } else {
-#pragma unroll
-        for (int u = 0; u < kGreedyWords; u++) {
-            const int e = s.eb + u * 64 + lane;
-            vv[u] = 0;
-            cc[u] = 0;
-            if (e < s.words) {
-                vv[u] = s.v[e];
-                cc[u] = C[cix[u]];
-            }
+    for (int u = 0; u < kGreedyWords; u++) {
+        const int e = u * 64 + lane;
+        vv[u] = 0;
+        cc[u] = 0;
+        if (e < s.words) {
+            vv[u] = s.v[e];
+            cc[u] = C[cix[u]];
         }
     }
     uint64_t cnt = 0;
 #pragma unroll
     for (int u = 0; u < kGreedyWords; u++)
         cnt += __popcll(vv[u] & ~cc[u]);
-    // further batches: positions advance by estep (and by 64 words within a
-    // batch) without division; a lane past the window's end reads its last
-    // word and counts nothing
-    if (kTail && all && s.eb + s.estep < s.words) {
-        const int sq = s.estep / nw1, sr = s.estep - sq * s.nw;
-        int row = (s.eb + lane) / nw1, col = s.eb + lane - row * s.nw;
-        const int last = s.words - 1;
-        const int64_t clast = (s.ylo + last / nw1) * W + s.w0 + (last - (last / nw1) * s.nw);
-        for (int e0 = s.eb + s.estep; e0 < s.words; e0 += s.estep) {
-            col += sr;
-            row += sq;
-            if (col >= s.nw) {
-                col -= s.nw;
-                row++;
-            }
-            uint64_t v2[kGreedyWords], c2[kGreedyWords];
-            int r = row, c = col;
-#pragma unroll
-            for (int u = 0; u < kGreedyWords; u++) {
-                const int e = e0 + u * 64 + lane;
-                const bool in = e < s.words;
-                v2[u] = s.v[in ? e : last];
-                c2[u] = C[in ? (s.ylo + r) * W + s.w0 + c : clast];
-                c += dr;
-                r += dq;
-                if (c >= s.nw) {
-                    c -= s.nw;
-                    r++;
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < kGreedyWords; u++) {
-                const int e = e0 + u * 64 + lane;
-                cnt += e < s.words ? __popcll(v2[u] & ~c2[u]) : 0;
-            }
-        }
-    }
     return cnt;
 }
 
-// C |= V over the share (the first batch from registers)
-template <bool kTail>
-__device__ __forceinline__ void share_or(const Share &s, uint64_t *C, int64_t W, int lane,
+// C |= V for a window of at most one batch, from the registers above
+__device__ __forceinline__ void share_or(const Share &s, uint64_t *C, int lane,
                                          const int64_t *cix, const uint64_t *vv,
                                          const uint64_t *cc)
 {
 #pragma unroll
     for (int u = 0; u < kGreedyWords; u++) {
-        const int e = s.eb + u * 64 + lane;
+        const int e = u * 64 + lane;
         if (e < s.words)
             C[cix[u]] = cc[u] | vv[u];
     }
-    if (!kTail || s.eb + s.estep >= s.words)
-        return;
+}
+
+// One wavefront's share of a large window (words >= 1), kWords words per
+// lane per batch, every load of a batch issued before the first wait: lanes
+// past the window's end read its last word and count (or store) nothing.
+// Positions advance by estep between batches and by 64 words within one,
+// without division.  kStore: C |= V instead of counting.
+template <int kWords, bool kStore>
+__device__ __forceinline__ uint64_t wide_pass(const Share &s, uint64_t *C, int64_t W, int lane)
+{
     const int nw1 = s.nw > 0 ? s.nw : 1;
     const int dq = 64 / nw1, dr = 64 - dq * s.nw;
     const int sq = s.estep / nw1, sr = s.estep - sq * s.nw;
     int row = (s.eb + lane) / nw1, col = s.eb + lane - row * s.nw;
     const int last = s.words - 1;
     const int64_t clast = (s.ylo + last / nw1) * W + s.w0 + (last - (last / nw1) * s.nw);
-    for (int e0 = s.eb + s.estep; e0 < s.words; e0 += s.estep) {
-        col += sr;
-        row += sq;
-        if (col >= s.nw) {
-            col -= s.nw;
-            row++;
-        }
-        uint64_t v2[kGreedyWords], c2[kGreedyWords];
-        int64_t ix[kGreedyWords];
+    uint64_t cnt = 0;
+    for (int e0 = s.eb; e0 < s.words; e0 += s.estep) {
+        uint64_t v2[kWords], c2[kWords];
+        int64_t ix[kWords];
         int r = row, c = col;
 #pragma unroll
-        for (int u = 0; u < kGreedyWords; u++) {
-            const int e = e0 + u * 64 + lane;
-            const bool in = e < s.words;
+        for (int u = 0; u < kWords; u++) {
+            const bool in = e0 + u * 64 + lane < s.words;
             ix[u] = in ? (s.ylo + r) * W + s.w0 + c : clast;
-            v2[u] = s.v[in ? e : last];
+            v2[u] = s.v[in ? e0 + u * 64 + lane : last];
             c2[u] = C[ix[u]];
             c += dr;
             r += dq;
@@ -331,13 +273,29 @@ __device__ __forceinline__ void share_or(const Share &s, uint64_t *C, int64_t W,
             }
         }
 #pragma unroll
-        for (int u = 0; u < kGreedyWords; u++) {
-            const int e = e0 + u * 64 + lane;
-            if (e < s.words)
-                C[ix[u]] = c2[u] | v2[u];
+        for (int u = 0; u < kWords; u++) {
+            const bool in = e0 + u * 64 + lane < s.words;
+            if (kStore) {
+                if (in)
+                    C[ix[u]] = c2[u] | v2[u];
+            } else {
+                cnt += in ? __popcll(v2[u] & ~c2[u]) : 0;
+            }
+        }
+        col += sr;
+        row += sq;
+        if (col >= s.nw) {
+            col -= s.nw;
+            row++;
         }
     }
+    return cnt;
 }
+
+// batch sizes of the large-window passes (words per lane; 32 for the count
+// was faster at ROI 1000 but slower at 200 and 500)
+constexpr int kWideCount = 16;
+constexpr int kWideOr = 16;
 
 // What wavefront 0 tells the helper wavefronts about a large window's round.
 struct BigRound {
@@ -386,13 +344,12 @@ __global__ __launch_bounds__(64 * kWaves) void greedy_run(
                 break;
             // the window's address from the kernel argument, so that its loads
             // stay global loads
-            const Share sh{bitmaps + rb.off, rb.ylo, rb.w0, rb.nw, rb.words, wave * kBatch,
-                           kWaves * kBatch};
-            int64_t cix[kGreedyWords];
-            uint64_t vv[kGreedyWords], cc[kGreedyWords];
-            const uint64_t cnt = share_count<true>(sh, C, W, rb.stale, lane, cix, vv, cc);
+            const uint64_t *v = bitmaps + rb.off;
             uint64_t gain = rb.g;
             if (rb.stale) {
+                const Share sc{v, rb.ylo, rb.w0, rb.nw, rb.words, wave * 64 * kWideCount,
+                               kWaves * 64 * kWideCount};
+                const uint64_t cnt = wide_pass<kWideCount, false>(sc, C, W, lane);
                 const uint32_t part = (uint32_t)wave_sum_u64(cnt);
                 if (lane == 0)
                     s_part[wave] = part;
@@ -405,8 +362,11 @@ __global__ __launch_bounds__(64 * kWaves) void greedy_run(
             }
             const uint64_t nk = (gain << 32) | (0xFFFFFFFFull - (uint64_t)rb.i);
             const bool take = gain > 0 && (!rb.stale || (nk > rb.second && nk > rb.bo));
-            if (take)
-                share_or<true>(sh, C, W, lane, cix, vv, cc);
+            if (take) {
+                const Share so{v, rb.ylo, rb.w0, rb.nw, rb.words, wave * 64 * kWideOr,
+                               kWaves * 64 * kWideOr};
+                wide_pass<kWideOr, true>(so, C, W, lane);
+            }
             __syncthreads();  // every share ORed into C
         }
         return;
@@ -510,12 +470,18 @@ __global__ __launch_bounds__(64 * kWaves) void greedy_run(
                                  stale ? 1 : 0, 0};
             __syncthreads();  // the helpers start
         }
-        const Share sh{v, w.ylo, w.w0, w.nw, words, 0, big ? kWaves * kBatch : kBatch};
+        const Share sh{v, w.ylo, w.w0, w.nw, words, 0, kBatch};
         int64_t cix[kGreedyWords];
         uint64_t vv[kGreedyWords], cc[kGreedyWords];
-        const uint64_t cnt = share_count<(kWaves > 1)>(sh, C, W, stale, lane, cix, vv, cc);
-        if (!big)
+        uint64_t cnt = 0;
+        if (big) {
+            if (stale)
+                cnt = wide_pass<kWideCount, false>(
+                    Share{v, w.ylo, w.w0, w.nw, words, 0, kWaves * 64 * kWideCount}, C, W, lane);
+        } else {
+            cnt = share_count(sh, C, W, lane, cix, vv, cc);
             block_other();
+        }
         uint64_t gain = g;
         if (stale) {
             uint32_t sum = (uint32_t)wave_sum_u64(cnt);
@@ -549,7 +515,11 @@ __global__ __launch_bounds__(64 * kWaves) void greedy_run(
             }
         }
         if (take) {
-            share_or<(kWaves > 1)>(sh, C, W, lane, cix, vv, cc);
+            if (big)
+                wide_pass<kWideOr, true>(
+                    Share{v, w.ylo, w.w0, w.nw, words, 0, kWaves * 64 * kWideOr}, C, W, lane);
+            else
+                share_or(sh, C, lane, cix, vv, cc);
             covered += (int64_t)gain;
             t++;
         }
