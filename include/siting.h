@@ -205,6 +205,19 @@ int siting_viewshed_batch(const int16_t *z, int64_t nrows, int64_t ncols, int64_
                           uint64_t *bitmaps, uint32_t *visible, uint32_t *cells,
                           void *ws, size_t ws_bytes, void *stream);
 
+/* Exact per-cell viewsheds, for measuring the sweep above against exact line
+ * of sight (the R3 family the paper cites as prior art; O(R^3) per observer,
+ * not part of the siting path): every lattice cell P of the ROI disk inside
+ * the terrain is visible iff the line of sight between the eye z[obs]+h_t
+ * and the receiver top z[P]+h_r is clear, by the test siting_vix describes;
+ * the observer's own cell is visible.  Same window layout and bitmaps as
+ * siting_viewshed_batch (offsets from siting_viewshed_layout; bitmaps device
+ * uint64[offsets[n]]); a record with a field out of range is skipped (its
+ * words are left untouched). */
+int siting_viewshed_r3(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
+                       const siting_observer *obs, int64_t n, const int64_t *offsets,
+                       uint64_t *bitmaps, void *stream);
+
 /* Times the candidate schedules of siting_viewshed_batch on the given
  * observers (synchronising the stream) and writes the fastest to
  * best_host; every candidate produces the same bits.  times_ms_host (may be

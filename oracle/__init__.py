@@ -57,6 +57,7 @@ def _load():
         lib.or_layout.restype = i64
         lib.or_viewshed_one.argtypes = [P, i64, i64, i64, P, P]
         lib.or_viewshed.argtypes = [P, i64, i64, i64, P, P, i64, i64, P]
+        lib.or_viewshed_r3.argtypes = [P, i64, i64, i64, P, P, i64, i64, P]
         lib.or_disk_cells.argtypes = [P, i64, i64]
         lib.or_disk_cells.restype = i64
         lib.or_viewshed_count.argtypes = [P, i64, i64, i64, P, i64, P, P]
@@ -177,6 +178,18 @@ def viewshed(z, obs, i0=0, i1=None):
     i1 = len(obs) if i1 is None else i1
     bm = np.zeros(int(off[-1]), np.uint64)
     _load().or_viewshed(_ptr(z), nr, nc, nc, _ptr(obs), _ptr(off), int(i0), int(i1), _ptr(bm))
+    return bm, off
+
+
+def viewshed_r3(z, obs, i0=0, i1=None):
+    """Exact per-cell viewsheds (every disk cell by its own line of sight,
+    the R3 family) of observers [i0, i1), in the layout of viewshed()."""
+    z, nr, nc = _terrain(z)
+    obs = np.ascontiguousarray(obs, OBSERVER_DTYPE)
+    off = layout(obs, nr, nc)
+    i1 = len(obs) if i1 is None else i1
+    bm = np.zeros(int(off[-1]), np.uint64)
+    _load().or_viewshed_r3(_ptr(z), nr, nc, nc, _ptr(obs), _ptr(off), int(i0), int(i1), _ptr(bm))
     return bm, off
 
 

@@ -435,6 +435,37 @@ void or_viewshed(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
         or_viewshed_one(z, nrows, ncols, ld, &obs[i], bitmaps + offsets[i]);
 }
 
+/* Exact per-cell viewshed (the R3 family the paper cites as prior art for
+ * viewsheds, and the definition the ray sweep approximates): every lattice
+ * cell P of the ROI disk inside the terrain is visible iff the line of sight
+ * from the observer to P is clear (or_los above); the observer's own cell is
+ * visible.  Same window layout as or_viewshed_one.                         */
+void or_viewshed_r3_one(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
+                        const or_observer *o, uint64_t *bm)
+{
+    int64_t xlo, xhi, ylo, yhi, w0, nw;
+    window(o, nrows, ncols, &xlo, &xhi, &ylo, &yhi, &w0, &nw);
+    memset(bm, 0, (size_t)((yhi - ylo + 1) * nw) * sizeof(uint64_t));
+    int64_t R = o->roi;
+    for (int64_t py = ylo; py <= yhi; py++)
+        for (int64_t px = xlo; px <= xhi; px++) {
+            int64_t dx = px - o->x, dy = py - o->y;
+            if (dx * dx + dy * dy > R * R)
+                continue;
+            if (or_los(z, nrows, ncols, ld, o->x, o->y, px, py, o->h_t, o->h_r))
+                setbit(bm, nw, w0, ylo, px, py);
+        }
+}
+
+void or_viewshed_r3(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
+                    const or_observer *obs, const int64_t *offsets, int64_t i0, int64_t i1,
+                    uint64_t *bitmaps)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = i0; i < i1; i++)
+        or_viewshed_r3_one(z, nrows, ncols, ld, &obs[i], bitmaps + offsets[i]);
+}
+
 /* Number of lattice cells of observer o's ROI disk inside the terrain. */
 int64_t or_disk_cells(const or_observer *o, int64_t nrows, int64_t ncols)
 {

@@ -65,6 +65,7 @@ def _load():
         "siting_viewshed_default_schedule": ([i32, P], C.c_int),
         "siting_viewshed_batch": ([P, i64, i64, i64, P, i64, P, P, i32, P, i32, P, P, P, P, sz, P],
                                   C.c_int),
+        "siting_viewshed_r3": ([P, i64, i64, i64, P, i64, P, P, P], C.c_int),
         "siting_autotune": ([P, i64, i64, i64, P, i64, P, P, i32, P, P, sz, P, P, P, i32],
                             C.c_int),
         "siting_autotune_candidates": ([i32, P, i32], C.c_int),
@@ -249,6 +250,21 @@ def siting_viewshed_batch(z, obs_dev, offsets_dev, rmax, order_dev=None, sched=N
         _ptr(cells) if sink == SITING_SINK_COUNT else None,
         _ptr(ws), ws.numel(), _stream(stream)))
     return bitmaps if sink == SITING_SINK_BITMAP else (visible, cells)
+
+
+def siting_viewshed_r3(z, obs_dev, offsets_dev, bitmaps=None, stream=None):
+    """Exact per-cell viewsheds (every disk cell by its own line of sight) in
+    the layout of siting_viewshed_batch.  Returns the bitmaps."""
+    import torch
+    nr, nc, ld = _dev_terrain(z)
+    n = obs_dev.shape[0]
+    if bitmaps is None:
+        total = int(offsets_dev[-1].item()) if n else 0
+        bitmaps = torch.zeros(max(total, 1), dtype=torch.int64, device=z.device)
+    _check("siting_viewshed_r3", _lib.siting_viewshed_r3(
+        _ptr(z), nr, nc, ld, _ptr(obs_dev), n, _ptr(offsets_dev), _ptr(bitmaps),
+        _stream(stream)))
+    return bitmaps
 
 
 def siting_autotune_candidates(rmax: int):

@@ -388,6 +388,50 @@ def test_viewshed_monotone_ring_and_d4(orc):
         assert got == {fwd(c) for c in base}, tr
 
 
+def test_viewshed_r3_brute_force_tiny(orc):
+    # the exact per-cell viewshed: every disk cell by the rational LOS of
+    # tests/brute.py, the observer's own cell visible
+    rng = np.random.default_rng(31)
+    for trial in range(40):
+        nr, nc = int(rng.integers(4, 24)), int(rng.integers(4, 24))
+        z = _rand_terrain(rng, nr, nc, 0, int(rng.integers(1, 60)))
+        x, y = int(rng.integers(0, nc)), int(rng.integers(0, nr))
+        R = int(rng.integers(1, 12))
+        ht, hr = int(rng.integers(0, 12)), int(rng.integers(0, 12))
+        ob = _obs(orc, x, y, R, ht, hr)
+        bm, off = orc.viewshed_r3(z, ob)
+        got = brute.bitmap_to_set(bm.reshape(-1, _nw(nc, x, R)), nr, nc, (x, y, R))
+        zl = z.tolist()
+        want = {c for c in brute.disk(nr, nc, x, y, R)
+                if c == (x, y) or brute.los(zl, (x, y), c, ht, hr)}
+        assert got == want, trial
+
+
+def _nw(nc, x, R):
+    return (min(nc - 1, x + R) >> 6) - (max(0, x - R) >> 6) + 1
+
+
+def test_viewshed_r3_flat_is_disk_and_wall(orc):
+    for (nr, nc, x, y, R, ht, hr) in [(40, 40, 20, 20, 13, 0, 0), (30, 70, 0, 5, 9, 7, 2),
+                                      (25, 25, 24, 24, 30, 0, 9)]:
+        z = np.full((nr, nc), 55, np.int16)
+        bm, _ = orc.viewshed_r3(z, _obs(orc, x, y, R, ht, hr))
+        got = brute.bitmap_to_set(bm.reshape(-1, _nw(nc, x, R)), nr, nc, (x, y, R))
+        assert got == brute.disk(nr, nc, x, y, R)
+    # a wall of height W one column a to the right: an x-major cell dx > a
+    # away is visible iff (hr - ht) * a >= (W - ht) * dx
+    nr, nc, tx, ty, R = 61, 61, 30, 30, 28
+    for W, a, ht, hr in [(40, 4, 10, 5), (12, 9, 10, 10)]:
+        z = np.zeros((nr, nc), np.int16)
+        z[:, tx + a] = W
+        bm, _ = orc.viewshed_r3(z, _obs(orc, tx, ty, R, ht, hr))
+        vis = brute.bitmap_to_set(bm.reshape(-1, _nw(nc, tx, R)), nr, nc, (tx, ty, R))
+        for dy in range(-R, R + 1):
+            for dx in range(a + 1, R + 1):
+                if dx * dx + dy * dy <= R * R and abs(dy) <= dx:
+                    assert ((tx + dx, ty + dy) in vis) == ((hr - ht) * a >= (W - ht) * dx)
+
+
 def test_viewshed_batch_layout_and_count(orc):
     z = fbm(100, 2.4, 500, 6)
     obs = uniform_observers(100, 100, 25, 3, roi=(3, 40), height=(0, 20))

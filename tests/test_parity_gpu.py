@@ -173,6 +173,24 @@ def test_viewshed_quadrant_mode(S, orc, seed, roi, shape):
     assert (cells.cpu().numpy().astype(np.uint32) == wc).all()
 
 
+@pytest.mark.parametrize("seed,roi,height,shape", [
+    (41, (1, 40), (0, 30), (200, 230)),
+    (42, (30, 90), (5, 100), (300, 280)),
+])
+def test_viewshed_r3_exact(S, orc, seed, roi, height, shape):
+    # exact per-cell viewsheds, edge windows and the corners included
+    _say("viewshed r3", seed, roi, shape)
+    nr, nc = shape
+    z = _terrain(nr, 2.3, 1200, seed, ncols=nc)
+    obs = _quadrant_observers(nr, nc, 60, seed, roi, height)
+    off = S.siting_viewshed_layout(obs, nr, nc)
+    got = S.siting_viewshed_r3(torch.from_numpy(z).cuda(), S.observers_to_device(obs),
+                               torch.from_numpy(off).cuda())
+    want, woff = orc.viewshed_r3(z, obs)
+    assert (woff == off).all()
+    assert (_u64(got)[:off[-1]] == want).all()
+
+
 def test_viewshed_every_schedule_same_bits(S, orc):
     from synth import uniform_observers
     z = _terrain(500, 2.4, 2000, 8)
