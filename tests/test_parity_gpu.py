@@ -308,3 +308,20 @@ def test_pipeline_plain_1000_end_to_end(S, orc):
     # coverage is non-decreasing and equals the union's popcount
     assert (np.diff(res.gains) <= 0).all()
     assert res.coverage_cells == sum(bin(int(v)).count("1") for v in cum.ravel())
+
+
+def test_lowered_accuracy_scoring(S, orc):
+    # siting on degraded terrains, scored on the full one: the exact run's
+    # own choice scores exactly its coverage; degraded runs score a valid area
+    from paper_2006_16783_amd import accuracy as A
+    from paper_2006_16783_amd import pipeline as P
+    cfg = P.SitingConfig("acc", 400, 2.4, 900, 3, 40, 10, 10, 10, 8, 5, 30, 1.0)
+    z = torch.from_numpy(_terrain(400, 2.4, 900, 3)).cuda()
+    xs, ys, _, res = A.site_degraded(z, cfg)
+    assert A.union_area(z, xs, ys, cfg) == res.coverage_cells
+    for q, f in [(20, 1), (1, 2)]:
+        xs, ys, _, r = A.site_degraded(z, cfg, q, f)
+        assert len(xs) == len(r.selected) > 0
+        assert (xs % f == 0).all() and (xs < 400).all() and (ys < 400).all()
+        area = A.union_area(z, xs, ys, cfg)
+        assert 0 < area <= 400 * 400
