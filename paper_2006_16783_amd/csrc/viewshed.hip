@@ -15,6 +15,11 @@
 //    wavefront of a pass is rarely nearly empty).  Observers above the
 //    schedule's stage_rmax read the terrain from global memory (L2 / Infinity
 //    Cache) instead.
+//  * Quadrant mode: when even the window bitmap exceeds LDS (ROI above 543),
+//    every observer of the launch is swept one quadrant at a time from global
+//    memory, the quadrant's bitmap in LDS; its words go out at once, ORed
+//    where an earlier quadrant wrote the same word (the observer's row and
+//    the word holding its column).
 //  * One ray per lane; consecutive lanes take consecutive boundary cells, so
 //    a wavefront's rays have similar lengths and similar LDS rows.
 //  * Exact integer slopes.  The per-quadrant elevation range bounds every
