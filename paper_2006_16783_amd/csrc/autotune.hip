@@ -47,8 +47,9 @@ extern "C" int siting_autotune_candidates(int32_t rmax, siting_schedule *out_hos
         int fit = std::max(1, std::min(16, budget / lds));
         for (int waves : {2, 4, 8, 16}) {
             // quadrant mode sweeps about 2R rays per quadrant: 8 or 16
-            // wavefronts; otherwise 2 to 8
-            if (quad ? waves < 8 : waves > 8)
+            // wavefronts; otherwise 2 to 8, and 16 where one workgroup fills
+            // the CU's LDS
+            if (quad ? waves < 8 : (waves > 8 && fit > 1))
                 continue;
             for (int g : {fit, std::max(1, fit / 2)}) {
                 siting_schedule s{waves, g, stage, 0};

