@@ -119,6 +119,47 @@ def cpu_baseline(z_host, obs, roi, seconds: float):
     }
 
 
+def cpu_per_core(seconds: float):
+    """The oracle's viewshed on one host thread, on the candidates of the
+    1000^2 (ROI 100) and 4096^2 (ROI 200) workloads (the first up to
+    `seconds`, the second a bounded prefix): cell-tests/s per core, the unit
+    of the paper's CPU figures."""
+    import numpy as np
+    import torch
+    import oracle
+    import paper_2006_16783_amd as S
+    from paper_2006_16783_amd import pipeline as P
+    from synth import fbm_torch
+    oracle.build()
+    out = {}
+    before = oracle.num_threads()
+    oracle.set_threads(1)
+    try:
+        for name in ("plain_1000", "batched_4096"):
+            cfg = P.CONFIGS[name]
+            z = fbm_torch(cfg.n, cfg.beta, cfg.zmax, cfg.seed, device="cuda")
+            cnt = S.siting_vix(z, cfg.roi, cfg.h_t, cfg.h_r, cfg.K, cfg.vix_seed)
+            cand = S.siting_findmax(cnt, z, cfg.grid, cfg.grid, cfg.k).cpu().numpy()
+            cand = cand[cand >= 0]
+            obs = oracle.observers(cand % cfg.n, cand // cfg.n, cfg.roi, cfg.h_t, cfg.h_r)
+            z_host = z.cpu().numpy()
+            done, cells, t_used, n = 0, 0, 0.0, 32
+            while done < len(obs) and t_used < seconds:
+                sub = obs[done:done + n]
+                t0 = time.perf_counter()
+                oracle.viewshed(z_host, sub)
+                t_used += time.perf_counter() - t0
+                cells += int(P.disk_cell_counts(sub, cfg.n, cfg.n).sum())
+                done += len(sub)
+                n *= 2
+            out[name] = {"cell_tests_per_s": cells / t_used, "candidates": done,
+                         "of": int(len(obs)), "seconds": t_used}
+    finally:
+        oracle.set_threads(before)
+    out["threads"] = 1
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -266,6 +307,8 @@ def main():
         z_host = z.cpu().numpy()
         cpu = cpu_baseline(z_host, last.observers, cfg.roi, args.cpu_seconds)
         del z_host
+        log("[bench] timing the oracle on one host thread (per-core figure)")
+        cpu["per_core"] = cpu_per_core(args.cpu_seconds / 3)
 
     out = {
         "metric": "viewshed cell-tests/s; siting wall-time at 46400², 4096 observers",

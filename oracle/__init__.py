@@ -66,6 +66,7 @@ def _load():
         lib.or_greedy_lazy.argtypes = [P, P, P, i64, i64, i64, i32, i64, P, P, P, P]
         lib.or_greedy_lazy.restype = i32
         lib.or_num_threads.restype = i32
+        lib.or_set_threads.argtypes = [i32]
         _lib = lib
     return _lib
 
@@ -92,6 +93,11 @@ def observers(x, y, roi, h_t, h_r) -> np.ndarray:
 
 def num_threads() -> int:
     return int(_load().or_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops (timing only)."""
+    _load().or_set_threads(int(n))
 
 
 def philox4x32_10(counter, key) -> np.ndarray:

@@ -615,3 +615,14 @@ int32_t or_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads for the parallel loops above (timing only; results do not depend
+ * on it): n >= 1. */
+void or_set_threads(int32_t n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
