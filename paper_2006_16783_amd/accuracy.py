@@ -57,7 +57,9 @@ def site_degraded(z, cfg, quant=1, coarsen=1):
     c = cfg
     if coarsen > 1:
         zd = zd[::coarsen, ::coarsen].contiguous()
-        c = dataclasses.replace(cfg, n=int(zd.shape[0]), roi=max(1, cfg.roi // coarsen))
+        nc_ = int(zd.shape[0])
+        c = dataclasses.replace(cfg, n=nc_, roi=max(1, cfg.roi // coarsen),
+                                grid=min(cfg.grid, nc_))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     res = P.run(zd, c, timing=False)

@@ -43,14 +43,15 @@ def compare(z, obs, rmax):
     torch.cuda.synchronize()
     a = r2.cpu().numpy().view(np.uint64)[:off[-1]]
     b = r3.cpu().numpy().view(np.uint64)[:off[-1]]
-    only2 = np.bitwise_count(a & ~b).astype(np.int64)
-    only3 = np.bitwise_count(b & ~a).astype(np.int64)
-    both = np.bitwise_count(a & b).astype(np.int64)
-    seg = off[:-1]
+    def per_observer(words):
+        # sums over each observer's words (an empty window sums to 0)
+        cs = np.concatenate([[0], np.cumsum(words.astype(np.int64))])
+        return cs[off[1:]] - cs[off[:-1]]
+
     out = {
-        "sweep_only": np.add.reduceat(only2, seg) if len(seg) else only2[:0],
-        "exact_only": np.add.reduceat(only3, seg) if len(seg) else only3[:0],
-        "both": np.add.reduceat(both, seg) if len(seg) else both[:0],
+        "sweep_only": per_observer(np.bitwise_count(a & ~b)),
+        "exact_only": per_observer(np.bitwise_count(b & ~a)),
+        "both": per_observer(np.bitwise_count(a & b)),
         "disk_cells": P.disk_cell_counts(obs, nr, nc),
     }
     return out, e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])
