@@ -42,7 +42,7 @@ extern "C" {
 enum {
     SITING_OK = 0,
     SITING_E_INVALID = -1,      /* bad argument (null pointer, range, shape) */
-    SITING_E_UNSUPPORTED = -2,  /* valid but beyond this build's limits */
+    SITING_E_UNSUPPORTED = -2,  /* valid but beyond the library's limits */
     SITING_E_HIP = -3,          /* a HIP runtime call failed */
     SITING_E_WORKSPACE = -4,    /* workspace missing or too small */
     SITING_E_INTERNAL = -5      /* internal invariant broken */
