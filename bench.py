@@ -13,7 +13,10 @@ Printed: ONE JSON line.  `value` is the viewshed throughput in cell-tests/s
 (in-disk in-terrain cells of all candidate viewsheds / viewshed stage time);
 `siting_wall_s` is the whole step's wall time (the second half of the
 metric).  `roofline` describes the dominant kernel of the step (VIX);
-`cpu_baseline` times the oracle on the host cores on a bounded sample.
+`cpu_baseline` times the oracle on the host cores on a bounded sample;
+`parity` compares the last timed step with the oracle (every viewshed and the
+oracle's SITE on its own bitmaps, VIX rows, every FINDMAX block), and the
+script exits with status 1 if they differ.
 """
 from __future__ import annotations
 
@@ -69,54 +72,93 @@ def traffic_from_profiles(kernel: str, src_hash: str):
         return None
 
 
-def cpu_baseline(z_host, obs, roi, seconds: float):
-    """The oracle's viewshed on a bounded sample of the candidates (cell-tests/s)
-    and its VIX on a few terrain rows (LOS tests/s), on this host's cores."""
+def cpu_baseline_and_parity(z_host, res, cfg, seconds: float, full_seconds: float):
+    """The oracle on this host's cores, on the outputs of the last timed step
+    (`res`, a pass run with keep=True), as both the CPU baseline and the
+    parity check of the timed run:
+      - viewsheds of the step's candidates in index order (cell-tests/s), each
+        window compared with the device's: all of them when they fit in
+        `full_seconds`, else a prefix of about `seconds` of work;
+      - once every window is computed, the oracle's greedy SITE on its own
+        bitmaps against the step's selection and gains;
+      - VIX on whole rows (LOS tests/s) against the step's counts;
+      - FINDMAX of every block, from the step's counts, against its candidates.
+    Returns (cpu_baseline, parity)."""
     import numpy as np
     import oracle
-    from paper_2006_16783_amd.pipeline import disk_cell_counts
+    from paper_2006_16783_amd.pipeline import disk_cell_counts, target_cells
     oracle.build()
     nr, nc = z_host.shape
-    rng = np.random.default_rng(0)
-    pick = rng.permutation(len(obs))
-    n = 256
-    t_used = 0.0
-    cells = 0
-    done = 0
-    while done < len(obs):
-        sub = obs[pick[done:done + n]]
+    obs, off = res.observers, res.offsets
+    M = len(obs)
+    dev_bm = res.bitmaps.cpu().numpy().view(np.uint64)
+    or_bm = np.zeros(int(off[-1]), np.uint64)
+    cells_all = disk_cell_counts(obs, nr, nc)
+    t_used, done, n, bad_windows = 0.0, 0, 256, 0
+    while done < M:
+        i1 = min(M, done + n)
         t0 = time.perf_counter()
-        oracle.viewshed(z_host, sub)
+        oracle.viewshed(z_host, obs, done, i1, out=or_bm)
         dt = time.perf_counter() - t0
         t_used += dt
-        cells += int(disk_cell_counts(sub, nr, nc).sum())
-        done += len(sub)
-        if t_used >= seconds * 0.6:
+        a, b = int(off[done]), int(off[i1])
+        if not (or_bm[a:b] == dev_bm[a:b]).all():
+            for i in range(done, i1):
+                bad_windows += int(not (or_bm[off[i]:off[i + 1]] == dev_bm[off[i]:off[i + 1]]).all())
+        done = i1
+        rate = int(cells_all[:done].sum()) / t_used
+        if t_used >= seconds and t_used + int(cells_all[done:].sum()) / rate > full_seconds:
             break
-        n = int(min(len(obs) - done, max(n, n * (seconds * 0.6 - t_used) / max(dt, 1e-3))))
-        if n <= 0:
-            break
+        n = int(max(n, min(M - done, n * 4)))
+    cells = int(cells_all[:done].sum())
     vs_rate = cells / t_used
-    # VIX: whole rows until ~40% of the budget
+    parity = {"viewsheds": f"{done - bad_windows}/{M}" + ("" if done == M else f" (first {done})"),
+              "viewshed_mismatches": bad_windows}
+    site_ok = None
+    if done == M:
+        sel, gains, _, _ = oracle.greedy(or_bm, off, obs, nr, nc, cfg.max_obs,
+                                         target_cells(cfg.target_frac, nr, nc), lazy=True)
+        site_ok = bool(len(sel) == len(res.selected) and (sel == res.selected).all() and
+                       (gains == res.gains).all())
+    parity["site"] = site_ok
+    del dev_bm, or_bm
+    # VIX: whole rows until ~40% of the budget, compared with the step's counts
     rows = 1
-    t_vix, tests = 0.0, 0
+    t_vix, tests, bad_rows = 0.0, 0, 0
     r0 = nr // 2
+    r_first = r0
     while t_vix < seconds * 0.4:
         t0 = time.perf_counter()
-        oracle.vix(z_host, roi, 10, 10, 10, 12345, rows=(r0, r0 + rows))
+        want = oracle.vix_rows(z_host, cfg.roi, cfg.h_t, cfg.h_r, cfg.K, cfg.vix_seed,
+                               np.arange(r0, r0 + rows))
         t_vix += time.perf_counter() - t0
-        tests += rows * nc * 10
+        got = res.key[r0:r0 + rows].cpu().numpy()
+        bad_rows += int((got != want).any(axis=1).sum())
+        tests += rows * nc * cfg.K
         r0 += rows
         rows *= 2
         if r0 + rows > nr:
             break
-    return {
+    nrows_v = r0 - r_first
+    parity["vix_rows"] = f"{nrows_v - bad_rows}/{nrows_v} (rows {r_first}..{r0 - 1})"
+    # FINDMAX: every block, ranked by the step's own counts
+    key_h = res.key.cpu().numpy()
+    cand = oracle.findmax(key_h, z_host, cfg.grid, cfg.grid, cfg.k)
+    del key_h
+    nblk = cfg.grid * cfg.grid
+    want_c = cand[cand >= 0]
+    fm_ok = len(want_c) == len(res.candidates) and bool((want_c == res.candidates).all())
+    parity["findmax_blocks"] = (f"{nblk}/{nblk}" if fm_ok else
+                                f"mismatch ({len(want_c)} vs {len(res.candidates)} candidates)")
+    parity["ok"] = bool(bad_windows == 0 and site_ok is not False and bad_rows == 0 and fm_ok)
+    cpu = {
         "value": vs_rate, "unit": "cell-tests/s", "cores": oracle.num_threads(), "kind": "oracle",
-        "sample": f"oracle viewsheds of {done} of the {len(obs)} candidates ({cells} cell-tests, "
-                  f"{t_used:.1f} s); oracle VIX on {tests // (10 * nc)} full rows "
+        "sample": f"oracle viewsheds of {done} of the {M} candidates ({cells} cell-tests, "
+                  f"{t_used:.1f} s); oracle VIX on {nrows_v} full rows "
                   f"({tests} LOS tests, {t_vix:.1f} s)",
         "vix_los_tests_per_s": tests / t_vix if t_vix > 0 else None,
     }
+    return cpu, parity
 
 
 def cpu_per_core(seconds: float):
@@ -167,7 +209,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="full_46400")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle leg (CPU baseline and parity check of the timed run)")
+    ap.add_argument("--parity-seconds", type=float, default=120.0,
+                    help="oracle viewsheds of every candidate when they fit in this time "
+                         "(then SITE is re-run by the oracle too)")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the viewshed schedule with the autotuner before timing")
     ap.add_argument("--schedule-cache", default=None,
@@ -230,7 +276,9 @@ def main():
     results = []
     t0 = time.perf_counter()
     for i in range(args.steps):
-        r = P.run(z, cfg, sched=sched)
+        # the last step keeps its device outputs for the parity check (the
+        # same work is enqueued either way)
+        r = P.run(z, cfg, sched=sched, keep=(i == args.steps - 1))
         results.append(r)
         for k, v in r.stage_ms.items():
             stage_tot[k] = stage_tot.get(k, 0.0) + v
@@ -246,7 +294,7 @@ def main():
 
     # dominant kernel: VIX.  Exact executed line-of-sight steps from the
     # counting variant (untimed), ALU ops per step as stated above.
-    _, los_steps, los_tests = S.siting_vix_stats(z, cfg.roi, cfg.h_t, cfg.h_r, cfg.K,
+    _, los_steps, los_tests, _ = S.siting_vix_stats(z, cfg.roi, cfg.h_t, cfg.h_r, cfg.K,
                                                  cfg.vix_seed)
     vix_s = stage_ms["vix"] / 1e3
     achieved = los_steps * VIX_OPS_PER_LOS_STEP / vix_s / 1e12
@@ -302,11 +350,14 @@ def main():
                "weights": "paper_2006_16783_amd/weights/surrogate_r100_h10.npy"}
 
     cpu = None
+    parity = None
     if not args.no_cpu_baseline:
-        log("[bench] timing the oracle on the host (bounded sample)")
+        log("[bench] timing the oracle on the host and checking the last step against it")
         z_host = z.cpu().numpy()
-        cpu = cpu_baseline(z_host, last.observers, cfg.roi, args.cpu_seconds)
+        cpu, parity = cpu_baseline_and_parity(z_host, last, cfg, args.cpu_seconds,
+                                              args.parity_seconds)
         del z_host
+        log(f"[bench] parity {parity}")
         log("[bench] timing the oracle on one host thread (per-core figure)")
         cpu["per_core"] = cpu_per_core(args.cpu_seconds / 3)
 
@@ -337,8 +388,12 @@ def main():
         "viewshed_roofline": vs_roof,
         "surrogate": sur,
         "cpu_baseline": cpu,
+        "parity": parity,
     }
     print(json.dumps(out), flush=True)
+    if parity is not None and not parity["ok"]:
+        log("[bench] the timed run differs from the oracle")
+        sys.exit(1)
 
 
 if __name__ == "__main__":

@@ -110,9 +110,14 @@ int siting_vix(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
                uint8_t *count, void *stream);
 
 /* The same computation as siting_vix (identical count output), in a
- * counting variant for measurement: stats (device, uint64[2]) receives the
- * number of line-of-sight steps executed (grid-line samples tested, up to and
- * including the first blocking one) and the number of line-of-sight tests.
+ * counting variant for measurement: stats (device, uint64[4]) receives
+ *   [0] the number of line-of-sight steps executed (grid-line samples
+ *       tested, up to and including the first blocking one),
+ *   [1] the number of line-of-sight tests,
+ *   [2], [3] the lowest and highest element offset from z (as int64) of any
+ *       terrain post the kernel reads from global memory, staging included
+ *       ([0, -1] if it reads none); every read lies in the terrain, i.e.
+ *       0 <= [2] and [3] <= (nrows-1)*ld + ncols-1.
  * Slower than siting_vix; not meant for production runs. */
 int siting_vix_stats(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
                      int32_t roi, int32_t h_t, int32_t h_r, int32_t K, uint64_t seed,
@@ -204,6 +209,17 @@ int siting_viewshed_batch(const int16_t *z, int64_t nrows, int64_t ncols, int64_
                           const siting_schedule *sched_host, int32_t sink,
                           uint64_t *bitmaps, uint32_t *visible, uint32_t *cells,
                           void *ws, size_t ws_bytes, void *stream);
+
+/* Exact visibility index of n observers from the counts of sink
+ * SITING_SINK_COUNT (Definitions: the fraction of the receivers within the
+ * ROI that are visible; the observer's own cell is not a receiver):
+ *     vi[i] = (visible[i] - 1) / (cells[i] - 1)
+ * as the correctly rounded float32 quotient of the two counts converted to
+ * float32 (exact conversions up to 2^24, i.e. every ROI <= 2310), and 0 when
+ * visible[i] = 0 or cells[i] <= 1 (a skipped record).
+ *   visible, cells : device uint32[n];  vi : out, device float[n]. */
+int siting_visibility_index(const uint32_t *visible, const uint32_t *cells, int64_t n,
+                            float *vi, void *stream);
 
 /* Exact per-cell viewsheds, for measuring the sweep above against exact line
  * of sight (the R3 family the paper cites as prior art; O(R^3) per observer,

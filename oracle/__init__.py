@@ -49,6 +49,7 @@ def _load():
         lib.or_los.argtypes = [P, i64, i64, i64, i64, i64, i64, i64, i32, i32]
         lib.or_los.restype = C.c_int
         lib.or_vix.argtypes = [P, i64, i64, i64, i32, i32, i32, i32, u64, P, i64, i64]
+        lib.or_vix_rowlist.argtypes = [P, i64, i64, i64, i32, i32, i32, i32, u64, P, i64, P]
         lib.or_vix_targets.argtypes = [i64, i64, i64, i64, i32, i32, u64, P, P]
         lib.or_findmax.argtypes = [P, i32, i32, P, i64, i64, i64, i32, i32, i32, P]
         lib.or_cell_max.argtypes = [P, i64, i64, i64, i32, i64, i64]
@@ -128,6 +129,18 @@ def vix(z, roi, h_t, h_r, K, seed, rows=None) -> np.ndarray:
     return out
 
 
+def vix_rows(z, roi, h_t, h_r, K, seed, rows) -> np.ndarray:
+    """The counts of vix() on the listed rows only: (len(rows), ncols)."""
+    z, nr, nc = _terrain(z)
+    rows = np.ascontiguousarray(rows, np.int64)
+    if len(rows) and (rows.min() < 0 or rows.max() >= nr):
+        raise ValueError("row outside the terrain")
+    out = np.zeros((len(rows), nc), np.uint8)
+    _load().or_vix_rowlist(_ptr(z), nr, nc, nc, int(roi), int(h_t), int(h_r), int(K),
+                           C.c_uint64(int(seed)), _ptr(rows), len(rows), _ptr(out))
+    return out
+
+
 def vix_targets(nrows, ncols, x, y, roi, K, seed):
     """The K receivers drawn for post (x, y); -1 marks a failed draw."""
     tx = np.zeros(K, np.int64)
@@ -175,14 +188,20 @@ def layout(obs, nrows, ncols) -> np.ndarray:
     return off
 
 
-def viewshed(z, obs, i0=0, i1=None):
+def viewshed(z, obs, i0=0, i1=None, out=None):
     """Window bitmaps of observers [i0, i1): stage Viewshed.  Returns
-    (bitmaps, offsets) with offsets over all observers."""
+    (bitmaps, offsets) with offsets over all observers; `out` (uint64, the
+    total words long) receives the windows in place of a new array."""
     z, nr, nc = _terrain(z)
     obs = np.ascontiguousarray(obs, OBSERVER_DTYPE)
     off = layout(obs, nr, nc)
     i1 = len(obs) if i1 is None else i1
-    bm = np.zeros(int(off[-1]), np.uint64)
+    if out is None:
+        bm = np.zeros(int(off[-1]), np.uint64)
+    else:
+        if out.dtype != np.uint64 or out.size < off[-1] or not out.flags.c_contiguous:
+            raise ValueError("out must be a contiguous uint64 array of the total words")
+        bm = out
     _load().or_viewshed(_ptr(z), nr, nc, nc, _ptr(obs), _ptr(off), int(i0), int(i1), _ptr(bm))
     return bm, off
 
@@ -222,6 +241,20 @@ def viewshed_count(z, obs):
     cells = np.zeros(len(obs), np.uint32)
     _load().or_viewshed_count(_ptr(z), nr, nc, nc, _ptr(obs), len(obs), _ptr(vis), _ptr(cells))
     return vis, cells
+
+
+def visibility_index(z, obs) -> np.ndarray:
+    """Exact visibility index of each observer (Definitions: the fraction of
+    the receivers within the ROI that are visible; the observer's own cell is
+    not a receiver): (visible - 1) / (cells - 1) from viewshed_count, as the
+    float32 quotient of the counts converted to float32 (0 for cells <= 1)."""
+    vis, cells = viewshed_count(z, obs)
+    num = (vis.astype(np.int64) - 1).astype(np.float32)
+    den = (cells.astype(np.int64) - 1).astype(np.float32)
+    ok = (vis >= 1) & (cells >= 2)
+    out = np.zeros(len(vis), np.float32)
+    out[ok] = num[ok] / den[ok]
+    return out
 
 
 def disk_cells(ob, nrows, ncols) -> int:

@@ -194,6 +194,21 @@ static int vix_draw(vix_stream *s, int32_t R, int64_t *ox, int64_t *oy)
     return 0;
 }
 
+/* The count of one post: K draws, each tested for line of sight. */
+static uint8_t vix_post(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld, int64_t x,
+                        int64_t y, int32_t R, int32_t h_t, int32_t h_r, int32_t K, uint64_t seed)
+{
+    int c = 0;
+    vix_stream st;
+    vix_stream_init(&st, nrows, ncols, x, y, R, seed);
+    for (int32_t j = 0; j < K; j++) {
+        int64_t px, py;
+        if (vix_draw(&st, R, &px, &py))
+            c += or_los(z, nrows, ncols, ld, x, y, px, py, h_t, h_r);
+    }
+    return (uint8_t)c;
+}
+
 /* Rows [row0,row1) of the count array (the full terrain when row0=0,
  * row1=nrows); count has nrows x ncols entries, row-major, contiguous.     */
 void or_vix(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
@@ -201,18 +216,26 @@ void or_vix(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
             uint8_t *count, int64_t row0, int64_t row1)
 {
 #pragma omp parallel for schedule(dynamic, 1)
-    for (int64_t y = row0; y < row1; y++) {
-        for (int64_t x = 0; x < ncols; x++) {
-            int c = 0;
-            vix_stream st;
-            vix_stream_init(&st, nrows, ncols, x, y, R, seed);
-            for (int32_t j = 0; j < K; j++) {
-                int64_t px, py;
-                if (vix_draw(&st, R, &px, &py))
-                    c += or_los(z, nrows, ncols, ld, x, y, px, py, h_t, h_r);
-            }
-            count[y * ncols + x] = (uint8_t)c;
-        }
+    for (int64_t y = row0; y < row1; y++)
+        for (int64_t x = 0; x < ncols; x++)
+            count[y * ncols + x] = vix_post(z, nrows, ncols, ld, x, y, R, h_t, h_r, K, seed);
+}
+
+/* The counts of the posts of rows rows[0..nlist) only, into count_rows
+ * (nlist x ncols, row-major); the work is split into chunks of columns so
+ * that a short list of long rows still spreads over the threads.           */
+void or_vix_rowlist(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
+                    int32_t R, int32_t h_t, int32_t h_r, int32_t K, uint64_t seed,
+                    const int64_t *rows, int64_t nlist, uint8_t *count_rows)
+{
+    const int64_t chunk = 4096, nch = (ncols + chunk - 1) / chunk;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t w = 0; w < nlist * nch; w++) {
+        int64_t i = w / nch, x0 = (w % nch) * chunk;
+        int64_t x1 = x0 + chunk < ncols ? x0 + chunk : ncols;
+        for (int64_t x = x0; x < x1; x++)
+            count_rows[i * ncols + x] = vix_post(z, nrows, ncols, ld, x, rows[i], R, h_t, h_r, K,
+                                                 seed);
     }
 }
 

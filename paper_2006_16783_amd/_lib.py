@@ -66,6 +66,7 @@ def _load():
         "siting_viewshed_batch": ([P, i64, i64, i64, P, i64, P, P, i32, P, i32, P, P, P, P, sz, P],
                                   C.c_int),
         "siting_viewshed_r3": ([P, i64, i64, i64, P, i64, P, P, P], C.c_int),
+        "siting_visibility_index": ([P, P, i64, P, P], C.c_int),
         "siting_autotune": ([P, i64, i64, i64, P, i64, P, P, i32, P, P, sz, P, P, P, i32],
                             C.c_int),
         "siting_autotune_candidates": ([i32, P, i32], C.c_int),
@@ -150,17 +151,18 @@ def siting_vix(z, roi, h_t, h_r, K, seed, count=None, stream=None):
 
 
 def siting_vix_stats(z, roi, h_t, h_r, K, seed, count=None, stream=None):
-    """Counting variant of siting_vix: returns (count, los_steps, los_tests)."""
+    """Counting variant of siting_vix: returns (count, los_steps, los_tests,
+    (lowest, highest) element offset of the terrain reads from global memory)."""
     import torch
     nr, nc, ld = _dev_terrain(z)
     if count is None:
         count = torch.empty((nr, nc), dtype=torch.uint8, device=z.device)
-    stats = torch.zeros(2, dtype=torch.int64, device=z.device)
+    stats = torch.zeros(4, dtype=torch.int64, device=z.device)
     _check("siting_vix_stats", _lib.siting_vix_stats(
         _ptr(z), nr, nc, ld, int(roi), int(h_t), int(h_r), int(K),
         C.c_uint64(int(seed) & (2**64 - 1)), _ptr(count), _ptr(stats), _stream(stream)))
     st = stats.cpu().tolist()
-    return count, int(st[0]), int(st[1])
+    return count, int(st[0]), int(st[1]), (int(st[2]), int(st[3]))
 
 
 def siting_findmax(key, z, grid_r, grid_c, k, key_stride=1, cand=None, stream=None):
@@ -250,6 +252,20 @@ def siting_viewshed_batch(z, obs_dev, offsets_dev, rmax, order_dev=None, sched=N
         _ptr(cells) if sink == SITING_SINK_COUNT else None,
         _ptr(ws), ws.numel(), _stream(stream)))
     return bitmaps if sink == SITING_SINK_BITMAP else (visible, cells)
+
+
+def siting_visibility_index(visible, cells, vi=None, stream=None):
+    """Exact visibility index (visible - 1) / (cells - 1) per observer from
+    the count sink's device counts (float32 device tensor)."""
+    import torch
+    n = visible.numel()
+    if cells.numel() != n:
+        raise ValueError("visible and cells differ in length")
+    if vi is None:
+        vi = torch.empty(max(n, 1), dtype=torch.float32, device=visible.device)
+    _check("siting_visibility_index", _lib.siting_visibility_index(
+        _ptr(visible), _ptr(cells), n, _ptr(vi), _stream(stream)))
+    return vi[:n]
 
 
 def siting_viewshed_r3(z, obs_dev, offsets_dev, bitmaps=None, stream=None):

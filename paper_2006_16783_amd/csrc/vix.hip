@@ -41,8 +41,6 @@
 // carry of one add), and the segment is E*n + (Z-E)*k; with |z| < 2^15,
 // n <= 4094 and heights <= 2^15 every term fits in int32 and the 24-bit
 // multipliers are exact.
-#include <cstdlib>
-
 #include "common.hpp"
 
 namespace siting {
@@ -54,6 +52,7 @@ constexpr int kVixChunk = 10;          // draws per post per queue round
 constexpr int kVixMaxAttempts = 64;    // consecutive rejections before a draw fails
 constexpr int kVixMaxRoi = 4094;       // queue entries hold dx, dy in 13 bits
 constexpr uint32_t kSkip = 0xFFFFFFFFu;
+constexpr int kSPI = 8;                // LOS steps per queue iteration
 
 // Count buffers per wavefront (batches in flight) and the LDS bytes besides
 // the tile: per wavefront kVixBufs x 64 8-bit visible counters (K <= 255).
@@ -115,8 +114,9 @@ __device__ __forceinline__ uint32_t lane_read(int src, uint32_t v)
 }
 
 // kLds: terrain tile staged in LDS (else global reads).  kCount: also count
-// executed LOS steps and tests.  kSPI: LOS steps per queue iteration.
-template <bool kLds, bool kCount, int kSPI>
+// executed LOS steps and tests, and record the lowest and highest terrain
+// element offsets the kernel reads from global memory.
+template <bool kLds, bool kCount>
 __global__ __launch_bounds__(kVixThreads) void vix_kernel(
     const int16_t *__restrict__ z, int64_t nrows, int64_t ncols, int64_t ld, int R, int h_t,
     int h_r, int K, uint64_t seed, uint8_t *__restrict__ count, int T, int64_t tiles_r,
@@ -126,6 +126,14 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_batch;
     uint64_t steps = 0, tests = 0;
+    // counting variant: element offsets (from z) of every global terrain read
+    int64_t rd_lo = INT64_MAX, rd_hi = INT64_MIN;
+    auto note = [&](int64_t o) {
+        if (kCount) {
+            rd_lo = o < rd_lo ? o : rd_lo;
+            rd_hi = o > rd_hi ? o : rd_hi;
+        }
+    };
     // XCD-aware tile order: workgroup b runs on XCD b % 8; give each XCD a
     // contiguous band of tiles.
     const int64_t b = blockIdx.x;
@@ -167,10 +175,13 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
                 for (int k0 = 0; k0 < dw_row; k0 += 64) {
                     const int k = k0 + lane;
                     const int64_t c = oxl + 2 * k;
-                    if (k < dw_row && (interior || (c >= 0 && c < ncols)))
+                    if (k < dw_row && (interior || (c >= 0 && c < ncols))) {
                         __builtin_amdgcn_global_load_lds(
                             reinterpret_cast<const uint32_t *>(srow + c), tdw + lr * dw_row + k0, 4,
                             0, 0);
+                        note(gy * ld + c);
+                        note(gy * ld + c + 1);
+                    }
                 }
             }
             __builtin_amdgcn_s_waitcnt(0);
@@ -180,14 +191,17 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
             for (int row = wave; row < h; row += kVixWaves) {
                 const int16_t *src = z + (gy0 + row) * ld + gx0;
                 int16_t *dst = tile + (gy0 + row - oy) * pitch + (gx0 - oxl);
-                for (int col = lane; col < w; col += 64)
+                for (int col = lane; col < w; col += 64) {
                     dst[col] = src[col];
+                    note((gy0 + row) * ld + gx0 + col);
+                }
             }
         }
     }
     __syncthreads();
     // terrain base: LDS tile origin (r0-H, oxl), or the global post (r0, c0)
     const int16_t *zb = kLds ? tile : z + r0 * ld + c0;
+    const int64_t zb_off = kLds ? 0 : r0 * ld + c0;  // zb's element offset in z (global reads)
     // LDS byte address of the tile
     const int tb = (int)(uint32_t)(uintptr_t)(const __attribute__((address_space(3))) char *)tile;
     const int rs = kLds ? pitch : (int)ld;
@@ -242,6 +256,8 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
         const int64_t y = r0 + py, x = c0 + px;
         po = kLds ? (py + H) * pitch + (px + (int)(c0 - oxl)) : py * (int)ld + px;
         Epost = valid ? (int)zb[po] + h_t : 0;
+        if (!kLds && valid)
+            note(zb_off + po);
         t = (uint64_t)(y * ncols + x);
         const int64_t bx0 = x - R < 0 ? 0 : x - R, bx1 = x + R > ncols - 1 ? ncols - 1 : x + R;
         const int64_t by0 = y - R < 0 ? 0 : y - R, by1 = y + R > nrows - 1 ? nrows - 1 : y + R;
@@ -335,15 +351,15 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
         atomicAdd(&cnt[cidx >> 2], 1u << ((cidx & 3) << 3));
     };
 
-    {
-        const int bt = claim();
-        if (bt >= nbatch)
-            return;
-        cur_bt = bt;
-        setup(bt);
+    bool more = true;  // further batches may remain in the tile
+    const int bt_first = claim();
+    // a wavefront that finds no batch left goes straight to the stats below
+    const bool have = bt_first < nbatch;
+    if (have) {
+        cur_bt = bt_first;
+        setup(bt_first);
         generate();
     }
-    bool more = true;  // further batches may remain in the tile
     bool active = false;
     // LOS state: n major steps, mn minor steps; e = r - n < 0 with r the
     // minor remainder, kept as an unsigned word so that e + mn >= 0 is the
@@ -377,9 +393,15 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
                 const int es = kLds ? 2 : 1;  // offset units per post
                 mn = xmaj ? ady : adx;
                 smaj = (xmaj ? sx : sy) * es;
-                smin = (xmaj ? sy : sx) * es;
+                // the second post of a sample is read at minor offset q+1; with
+                // no minor extent its weight r is always 0 and q+1 would leave
+                // the observer-receiver box (past the terrain's last row or
+                // column), so it is read at offset q instead
+                smin = mn == 0 ? 0 : (xmaj ? sy : sx) * es;
                 const int tgt = spo + (kLds ? mul_i24(dy, rs) : dy * rs) + dx;
                 const int Zt = (int)zb[tgt] + h_r;
+                if (!kLds)
+                    note(zb_off + tgt);
                 off = kLds ? tb + spo * 2 : spo;
                 rhs = mul_i24(sE, n);  // |sE| < 2^17, n < 2^14
                 dz = Zt - sE;
@@ -414,8 +436,12 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
                 sa[sp] = 0;
                 sb[sp] = 0;
                 if (sp < k) {
+                    // both posts lie in the observer-receiver box: minor
+                    // offsets q and q+1 <= |minor| (q+1 = q when |minor| = 0)
                     sa[sp] = zb[off];
-                    sb[sp] = zb[off + smin];  // in the observer-target box
+                    sb[sp] = zb[off + smin];
+                    note(zb_off + off);
+                    note(zb_off + off + smin);
                 }
             }
         }
@@ -441,7 +467,7 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
         }
     };
 
-    for (;;) {
+    for (; have;) {
         // the hot loop: the queue holds tests
         while (cursor < total) {
             take();
@@ -488,13 +514,21 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
         // no new tests yet (or none left): advance the running ones
         step_block();
     }
-    retire(buf, cur_bt);
-    for (int bf = 0; bf < kVixBufs; bf++)
-        if (pending & (1u << bf))
-            retire(bf, (int)((bt_of >> (16 * bf)) & 0xFFFF));
+    if (have) {
+        retire(buf, cur_bt);
+        for (int bf = 0; bf < kVixBufs; bf++)
+            if (pending & (1u << bf))
+                retire(bf, (int)((bt_of >> (16 * bf)) & 0xFFFF));
+    }
     if (kCount) {
         atomicAdd(&stats[0], (unsigned long long)steps);
         atomicAdd(&stats[1], (unsigned long long)tests);
+        // offsets as signed values biased by 2^63, so that an unsigned
+        // minimum/maximum orders them (a negative offset stays below 0)
+        if (rd_lo <= rd_hi) {
+            atomicMin(&stats[2], (unsigned long long)rd_lo ^ (1ull << 63));
+            atomicMax(&stats[3], (unsigned long long)rd_hi ^ (1ull << 63));
+        }
     }
 }
 
@@ -502,6 +536,20 @@ __global__ void vix_stats_reset(unsigned long long *stats)
 {
     stats[0] = 0;
     stats[1] = 0;
+    stats[2] = ~0ull;
+    stats[3] = 0;
+}
+
+// stats[2..3] back from the biased form; an empty range reads as [0, -1]
+__global__ void vix_stats_finish(unsigned long long *stats)
+{
+    if (stats[2] > stats[3]) {
+        stats[2] = 0;
+        stats[3] = ~0ull;
+    } else {
+        stats[2] ^= 1ull << 63;
+        stats[3] ^= 1ull << 63;
+    }
 }
 
 }  // namespace
@@ -529,17 +577,12 @@ static int vix_launch(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld
         set_error("%s: roi %d above the supported %d", fn, roi, kVixMaxRoi);
         return SITING_E_UNSUPPORTED;
     }
-    static const int spi = [] {
-        const char *e = getenv("SITING_VIX_STEPS_PER_ITER");
-        int v = e ? atoi(e) : 8;
-        return v == 2 ? 2 : v == 4 ? 4 : 8;
-    }();
     // Largest tile side (multiple of 8, <= 128) whose haloed tile (halo: the
-    // ROI plus spi-1 steps past a line's end) and the count buffers fit in
+    // ROI plus kSPI-1 steps past a line's end) and the count buffers fit in
     // LDS (every instantiation declares the same static LDS).
-    const int lds_max = kernel_max_dynamic_lds(reinterpret_cast<const void *>(&vix_kernel<true, false, 8>));
+    const int lds_max = kernel_max_dynamic_lds(reinterpret_cast<const void *>(&vix_kernel<true, false>));
     const int queue_bytes = kVixWaves * kVixWaveLds;
-    const int halo = roi + spi - 1;
+    const int halo = roi + kSPI - 1;
     int T = 0;
     for (int c = 128; c >= 16; c -= 8) {
         int64_t bytes = (((int64_t)(c + 2 * halo) * (c + 2 * halo + 2) * 2 + 15) & ~15ll) + queue_bytes;
@@ -575,30 +618,25 @@ static int vix_launch(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld
         if (rc != SITING_OK)
             return rc;
     }
-#define VIX_LAUNCH(LDS, CNT, SPI)                                                              \
-    hipLaunchKernelGGL((vix_kernel<LDS, CNT, SPI>), dim3((unsigned)grid), dim3(kVixThreads),   \
-                       lds, s, z, nrows, ncols, ld, roi, h_t, h_r, K, seed, count, T, tiles_r,  \
-                       tiles_c, per_xcd, tile_bytes, dma, stats)
-#define VIX_SPI(LDS, CNT)                    \
-    do {                                     \
-        if (spi == 2)                        \
-            VIX_LAUNCH(LDS, CNT, 2);         \
-        else if (spi == 8)                   \
-            VIX_LAUNCH(LDS, CNT, 8);         \
-        else                                 \
-            VIX_LAUNCH(LDS, CNT, 4);         \
-    } while (0)
+#define VIX_LAUNCH(LDS, CNT)                                                                   \
+    hipLaunchKernelGGL((vix_kernel<LDS, CNT>), dim3((unsigned)grid), dim3(kVixThreads), lds, s, \
+                       z, nrows, ncols, ld, roi, h_t, h_r, K, seed, count, T, tiles_r, tiles_c,  \
+                       per_xcd, tile_bytes, dma, stats)
     if (use_lds && stats)
-        VIX_SPI(true, true);
+        VIX_LAUNCH(true, true);
     else if (use_lds)
-        VIX_SPI(true, false);
+        VIX_LAUNCH(true, false);
     else if (stats)
-        VIX_SPI(false, true);
+        VIX_LAUNCH(false, true);
     else
-        VIX_SPI(false, false);
-#undef VIX_SPI
+        VIX_LAUNCH(false, false);
 #undef VIX_LAUNCH
-    return check_launch("vix_kernel");
+    int rc = check_launch("vix_kernel");
+    if (rc == SITING_OK && stats) {
+        hipLaunchKernelGGL(vix_stats_finish, dim3(1), dim3(1), 0, s, stats);
+        rc = check_launch("vix_stats_finish");
+    }
+    return rc;
 }
 
 extern "C" int siting_vix(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld, int32_t roi,

@@ -74,6 +74,11 @@ class SitingResult:
     stage_ms: dict = field(default_factory=dict)
     cell_tests: int = 0
     schedule: tuple | None = None
+    # with run(..., keep=True): the device tensors of the pass (FINDMAX key,
+    # window bitmaps, cumulative viewshed), for checking its outputs
+    key: object = None
+    bitmaps: object = None
+    cumulative: object = None
 
 
 def target_cells(frac: float, nrows: int, ncols: int) -> int:
@@ -184,12 +189,13 @@ class _Timer:
 
 
 def run(z, cfg: SitingConfig, key=None, key_stride=1, sched=None, timing=True,
-        surrogate=None) -> SitingResult:
+        surrogate=None, keep=False) -> SitingResult:
     """One pass of the whole siting path over the device terrain z (int16,
     resident in HBM).  The FINDMAX ranking is the VIX count, or `key` (a
     float32 device tensor) when given, or the CNN score of the cells of a
     stride grid when surrogate=(params, stride) is given (computed inside the
-    timed pass)."""
+    timed pass).  keep=True also returns the pass's device tensors (no extra
+    work is enqueued)."""
     import torch
     nrows, ncols = z.shape
     dev = z.device
@@ -222,6 +228,9 @@ def run(z, cfg: SitingConfig, key=None, key_stride=1, sched=None, timing=True,
     sel_h = sel[:m].cpu().numpy()
     gains_h = gains[:m].cpu().numpy()
     T.mark("end")
-    return SitingResult(selected=sel_h, gains=gains_h, candidates=cand_h, observers=obs,
-                        offsets=off, coverage_cells=int(gains_h.sum()), stage_ms=T.result(),
-                        schedule=None if sched is None else sched.as_tuple())
+    res = SitingResult(selected=sel_h, gains=gains_h, candidates=cand_h, observers=obs,
+                       offsets=off, coverage_cells=int(gains_h.sum()), stage_ms=T.result(),
+                       schedule=None if sched is None else sched.as_tuple())
+    if keep:
+        res.key, res.bitmaps, res.cumulative = key, bm, cum
+    return res

@@ -53,9 +53,7 @@ def exact_vi(z, centres, roi: int, h: int):
     obs["roi"], obs["h_t"], obs["h_r"] = roi, h, h
     vis, cells = L.siting_viewshed_batch(z, L.observers_to_device(obs, z.device), None, roi,
                                          sink=L.SITING_SINK_COUNT)
-    vis = vis[:len(c)].to(torch.float32)
-    cells = cells[:len(c)].to(torch.float32)
-    return ((vis - 1.0) / (cells - 1.0).clamp_min(1.0)).contiguous()
+    return L.siting_visibility_index(vis[:len(c)], cells[:len(c)])
 
 
 @dataclass

@@ -56,6 +56,12 @@ def test_validation_errors_before_launch():
     assert lib.siting_greedy(fake, fake, fake, 0, 10, 10, 3, 100, fake, fake, fake, fake,
                              fake, 1 << 20, None) == -1
     assert lib.siting_greedy_workspace_size(100) >= 100 * 12
+    # visibility index: negative count, NULL pointers; nothing to do for n = 0
+    assert lib.siting_visibility_index(fake, fake, -1, fake, None) == -1
+    assert lib.siting_visibility_index(None, fake, 5, fake, None) == -1
+    assert lib.siting_visibility_index(None, None, 0, None, None) == 0
+    # the counting VIX variant needs its stats buffer
+    assert lib.siting_vix_stats(fake, 10, 10, 10, 5, 1, 1, 4, 0, fake, None, None) == -1
 
 
 def test_layout_matches_oracle_and_rejects_bad_observers(orc):

@@ -77,6 +77,24 @@ def test_patch_centre_and_clamp():
     assert P[1, 0, 0] == (-32 * 90 - 32) / 256
 
 
+def test_adam_constant_gradient_moves_lr_per_step():
+    # with a constant gradient g the bias-corrected moments are exactly g and
+    # g^2 at every step (m_t = (1 - b1^t) g, v_t = (1 - b2^t) g^2), so every
+    # step moves each parameter by lr * g / (|g| + eps): the bias correction
+    # of Adam (Kingma & Ba, Algorithm 1) pinned at steps 1..50, not just the first
+    rng = np.random.default_rng(5)
+    theta0 = rng.standard_normal(12)
+    g = rng.standard_normal(12) * np.logspace(-3, 2, 12)
+    lr, eps = 0.003, 1e-8
+    theta, m, v = theta0.copy(), np.zeros(12), np.zeros(12)
+    for step in range(1, 51):
+        prev = theta
+        theta, m, v = cnn.adam(theta, m, v, g, step, lr, eps=eps)
+        assert np.allclose(prev - theta, lr * g / (np.abs(g) + eps), rtol=1e-9, atol=1e-15), step
+    assert np.allclose(theta, theta0 - 50 * lr * g / (np.abs(g) + eps), rtol=0, atol=1e-12)
+    assert np.allclose(theta, theta0 - 50 * lr * np.sign(g), rtol=0, atol=1e-5)
+
+
 def test_adam_first_step_is_signed_lr():
     rng = np.random.default_rng(3)
     theta = rng.standard_normal(10)

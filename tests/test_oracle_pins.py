@@ -136,16 +136,27 @@ def test_vix_draw_stream_layout(orc):
                 words += [int(w) for w in orc.philox4x32_10(ctr, key)]
             a = 0
             for j in range(9):
-                while True:
+                # at most 64 proposals per draw; a draw with none accepted
+                # fails (-1) and the next draw starts at the following word
+                px = py = -1
+                for _ in range(64):
                     u = words[a]
                     a += 1
                     mx, my = (u & 0xffff) * wx, (u >> 16) * wy
                     if (mx & 0xffff) < 65536 % wx or (my & 0xffff) < 65536 % wy:
                         continue
-                    px, py = bx0 + (mx >> 16), by0 + (my >> 16)
-                    if (px, py) != (x, y) and (px - x) ** 2 + (py - y) ** 2 <= R * R:
+                    qx, qy = bx0 + (mx >> 16), by0 + (my >> 16)
+                    if (qx, qy) != (x, y) and (qx - x) ** 2 + (qy - y) ** 2 <= R * R:
+                        px, py = qx, qy
                         break
                 assert (tx[j], ty[j]) == (px, py), (x, y, j)
+
+
+def test_vix_rowlist_equals_whole_terrain_rows(orc):
+    z = fbm(90, 2.4, 600, 4)
+    full = orc.vix(z, 12, 5, 3, 7, 31)
+    rows = [89, 0, 44, 45, 3]
+    assert (orc.vix_rows(z, 12, 5, 3, 7, 31, rows) == full[rows]).all()
 
 
 def test_lemire_scaling_is_exactly_uniform():

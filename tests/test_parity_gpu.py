@@ -40,14 +40,44 @@ def _u64(t):
     ((64, 64), 100, 10, 10, 10, 5),      # ROI larger than the terrain
     ((421, 380), 140, 25, 3, 6, 7),      # too big for an LDS tile: global reads
     ((520, 610), 30, 5, 15, 23, 11),     # several chunks and batches per wavefront
+    ((257, 301), 12, 10, 10, 10, (3 << 32) | 17),  # seed above 2^32: key word 1 non-zero
 ])
 def test_vix_parity(S, orc, shape, R, ht, hr, K, seed):
     _say("vix", shape, R, ht, hr, K, seed)
-    z = _terrain(shape[0], 2.4, 1500, seed, ncols=shape[1])
+    z = _terrain(shape[0], 2.4, 1500, seed % 1000, ncols=shape[1])
     zd = torch.from_numpy(z).cuda()
-    got = S.siting_vix(zd, R, ht, hr, K, seed * 7919).cpu().numpy()
-    want = orc.vix(z, R, ht, hr, K, seed * 7919)
+    vseed = seed * 7919 if seed < 2 ** 32 else seed
+    got = S.siting_vix(zd, R, ht, hr, K, vseed).cpu().numpy()
+    want = orc.vix(z, R, ht, hr, K, vseed)
     assert (got == want).all(), int((got != want).sum())
+
+
+@pytest.mark.parametrize("shape,ld,R", [((300, 310), 310, 140), ((257, 200), 203, 150)])
+def test_vix_global_reads_stay_in_the_terrain(S, orc, shape, ld, R):
+    # ROI above the largest LDS tile: the kernel reads the terrain through the
+    # cache hierarchy.  Lines of sight along a row or column end at posts of
+    # the last row or column; the counting variant records the lowest and
+    # highest element offset it reads, which must stay in the terrain (the
+    # allocation is exactly nrows * ld - (ld - ncols) posts long).
+    nr, nc = shape
+    z = _terrain(nr, 2.4, 900, 17, ncols=nc)
+    flat = torch.zeros(nr * ld - (ld - nc), dtype=torch.int16, device="cuda")
+    view = torch.as_strided(flat, (nr, nc), (ld, 1))
+    view.copy_(torch.from_numpy(z).cuda())
+    cnt, steps, tests, (lo, hi) = S.siting_vix_stats(view, R, 10, 10, 12, 5)
+    _say("vix global reads", shape, ld, R, lo, hi, steps, tests)
+    assert 0 <= lo <= hi <= (nr - 1) * ld + nc - 1, (lo, hi)
+    assert lo == 0 and hi == (nr - 1) * ld + nc - 1   # the corners are read (own posts)
+    assert (cnt.cpu().numpy() == orc.vix(z, R, 10, 10, 12, 5)).all()
+    assert (S.siting_vix(view, R, 10, 10, 12, 5).cpu().numpy() == cnt.cpu().numpy()).all()
+
+
+def test_vix_lds_tile_reads_stay_in_the_terrain(S):
+    # the LDS-tiled path reads the terrain only while staging tiles
+    z = _terrain(300, 2.4, 900, 18, ncols=262)
+    zd = torch.from_numpy(z).cuda()
+    _, _, _, (lo, hi) = S.siting_vix_stats(zd, 30, 10, 10, 10, 5)
+    assert lo == 0 and hi == 300 * 262 - 1
 
 
 def test_vix_strided_terrain(S, orc):
@@ -288,6 +318,66 @@ def test_greedy_large_windows(S, orc, seed, n_obs, roi):
     assert (sel[:m].cpu().numpy() == wsel).all()
     assert (gains[:m].cpu().numpy() == wgain).all()
     assert (_u64(cum).reshape(-1) == wcum.reshape(-1)).all()
+
+
+def test_greedy_ties_on_flat_terrain(S, orc):
+    # flat terrain: equal disks everywhere.  Observers on a lattice of spacing
+    # 2R+1 never overlap, so every round is a tie among all unselected ones
+    # and the selection is their indices in increasing order; a second group
+    # overlaps the first and duplicates some of its posts (ties at lower
+    # gains, and zero gains once a duplicate's twin is in).
+    n, R = 300, 12
+    z = np.full((n, n), 250, np.int16)
+    rng = np.random.default_rng(3)
+    pts = [(x, y) for y in range(R, n - R, 2 * R + 1) for x in range(R, n - R, 2 * R + 1)]
+    rng.shuffle(pts)
+    lattice = orc.observers([p[0] for p in pts], [p[1] for p in pts], R, 10, 10)
+    bm_h, off = orc.viewshed(z, lattice)
+    ones = np.bitwise_count(bm_h).astype(np.int64)
+    sizes = np.add.reduceat(ones, off[:-1])
+    assert (sizes == sizes[0]).all()          # every gain ties at first
+    sel, gains, _ = _greedy_both(S, orc, z, lattice, len(lattice) + 5, n * n)
+    assert (sel == np.arange(len(lattice))).all() and (gains == sizes[0]).all()
+    dup = lattice[rng.permutation(len(lattice))[:20]]
+    shifted = lattice[:30].copy()
+    shifted["x"] += 6
+    mixed = np.concatenate([dup, lattice, shifted, dup])
+    sel, gains, _ = _greedy_both(S, orc, z, mixed, 200, n * n)
+    assert (np.diff(gains) <= 0).all() and len(sel) < len(mixed)
+
+
+def _greedy_both(S, orc, z, obs, max_obs, tgt):
+    nr, nc = z.shape
+    bm_h, off = orc.viewshed(z, obs)
+    wsel, wgain, wcum, _ = orc.greedy(bm_h, off, obs, nr, nc, max_obs, tgt, lazy=True)
+    psel, pgain, _ = orc.greedy(bm_h, off, obs, nr, nc, max_obs, tgt)
+    assert (psel == wsel).all() and (pgain == wgain).all()
+    zd = torch.from_numpy(z).cuda()
+    obs_d = S.observers_to_device(obs)
+    off_d = torch.from_numpy(off).cuda()
+    bm = S.siting_viewshed_batch(zd, obs_d, off_d, int(obs["roi"].max()))
+    assert (_u64(bm)[:off[-1]] == bm_h).all()
+    sel, gains, nsel, cum = S.siting_greedy(bm, off_d, obs_d, nr, nc, max_obs, tgt)
+    m = int(nsel.item())
+    assert m == len(wsel)
+    assert (sel[:m].cpu().numpy() == wsel).all() and (gains[:m].cpu().numpy() == wgain).all()
+    assert (_u64(cum).reshape(-1) == wcum.reshape(-1)).all()
+    return wsel, wgain, wcum
+
+
+def test_visibility_index_labels(S, orc):
+    # the exact visibility index (visible - 1) / (cells - 1) from the count
+    # sink, clipped windows included, bit for bit against the oracle's
+    # float32 quotient of its own counts
+    from synth import uniform_observers
+    z = _terrain(350, 2.4, 1500, 23)
+    obs = uniform_observers(350, 350, 400, 23, roi=(1, 120), height=(0, 40))
+    vis, cells = S.siting_viewshed_batch(torch.from_numpy(z).cuda(), S.observers_to_device(obs),
+                                         None, 120, sink=S.SITING_SINK_COUNT)
+    vi = S.siting_visibility_index(vis[:len(obs)], cells[:len(obs)]).cpu().numpy()
+    want = orc.visibility_index(z, obs)
+    assert vi.dtype == np.float32 and (vi.view(np.uint32) == want.view(np.uint32)).all()
+    assert (vi >= 0).all() and (vi <= 1).all()
 
 
 # ------------------------------------------------------------- PIPELINE ----
