@@ -276,6 +276,23 @@ int siting_greedy(const uint64_t *bitmaps, const int64_t *offsets, const siting_
                   uint64_t *cumulative, int64_t *selected, int64_t *gains, int32_t *nselected,
                   void *ws, size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * selection as siting_greedy, identical outputs, without a workspace
+ * argument.  Its state lives in a static device array the library holds on
+ * each device until the process ends, sized for up to
+ * SITING_GREEDY_NOALLOC_MAX_N candidates (about 12.6 MB); n above that
+ * returns SITING_E_UNSUPPORTED.  The call allocates nothing (no hipMalloc,
+ * no library allocation).  Every call on one device shares that device's
+ * array, which keeps the last call's contents (each call rewrites what it
+ * reads, so nothing needs clearing): calls that overlap on one device, on
+ * any streams, race and must be serialised by the caller. */
+#define SITING_GREEDY_NOALLOC_MAX_N 1048576
+int siting_greedy_noalloc(const uint64_t *bitmaps, const int64_t *offsets,
+                          const siting_observer *obs, int64_t n, int64_t nrows, int64_t ncols,
+                          int32_t max_obs, int64_t target_cells, uint64_t *cumulative,
+                          int64_t *selected, int64_t *gains, int32_t *nselected, void *stream);
+
 /* ------------------------------------------------------ LEARNED RANKING ----
  * A small CNN predicting a post's visibility index (Definitions: the visible
  * fraction of the ROI receivers) from the 64 x 64 patch around it, used only

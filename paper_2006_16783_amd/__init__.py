@@ -11,7 +11,8 @@ from ._lib import (SitingError, Schedule, OBSERVER_DTYPE, SITING_KEY_U8, SITING_
                    siting_vix, siting_vix_stats, siting_findmax, siting_viewshed_layout, siting_viewshed_order,
                    siting_viewshed_workspace_size, siting_viewshed_default_schedule,
                    siting_viewshed_batch, siting_viewshed_r3, siting_visibility_index, siting_autotune, siting_autotune_candidates,
-                   siting_greedy_workspace_size, siting_greedy, observers_to_device,
+                   siting_greedy_workspace_size, siting_greedy, siting_greedy_noalloc,
+                   SITING_GREEDY_NOALLOC_MAX_N, observers_to_device,
                    siting_cnn_param_count, siting_cnn_workspace_size, siting_cnn_forward,
                    siting_cnn_backward, siting_cnn_adam, siting_cnn_score_terrain, cnn_workspace)
 

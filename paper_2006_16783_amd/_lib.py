@@ -72,6 +72,7 @@ def _load():
         "siting_autotune_candidates": ([i32, P, i32], C.c_int),
         "siting_greedy_workspace_size": ([i64], sz),
         "siting_greedy": ([P, P, P, i64, i64, i64, i32, i64, P, P, P, P, P, sz, P], C.c_int),
+        "siting_greedy_noalloc": ([P, P, P, i64, i64, i64, i32, i64, P, P, P, P, P], C.c_int),
         "siting_cnn_param_count": ([], C.c_int),
         "siting_cnn_workspace_size": ([i64], sz),
         "siting_cnn_forward": ([P, P, i64, i64, i64, P, i64, P, P, sz, P], C.c_int),
@@ -331,6 +332,22 @@ def siting_greedy(bitmaps, offsets_dev, obs_dev, nrows, ncols, max_obs, target_c
         int(target_cells), _ptr(cumulative), _ptr(selected), _ptr(gains), _ptr(nsel), _ptr(ws),
         ws.numel(), _stream(stream)))
     return selected, gains, nsel, cumulative
+
+
+SITING_GREEDY_NOALLOC_MAX_N = 1048576
+
+
+def siting_greedy_noalloc(bitmaps, offsets_dev, obs_dev, nrows, ncols, max_obs, target_cells,
+                          cumulative, selected, gains, nselected, stream=None):
+    """Greedy SITE into caller-owned outputs (cumulative: nrows x
+    ceil(ncols/64) words; selected, gains: int64[max_obs]; nselected:
+    int32[1]), with the library's static workspace: nothing is allocated."""
+    n = obs_dev.shape[0]
+    _check("siting_greedy_noalloc", _lib.siting_greedy_noalloc(
+        _ptr(bitmaps), _ptr(offsets_dev), _ptr(obs_dev), n, int(nrows), int(ncols), int(max_obs),
+        int(target_cells), _ptr(cumulative), _ptr(selected), _ptr(gains), _ptr(nselected),
+        _stream(stream)))
+    return selected, gains, nselected, cumulative
 
 
 # ---------------------------------------------------------------- CNN ------

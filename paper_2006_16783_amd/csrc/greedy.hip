@@ -30,6 +30,7 @@
 // the OR, which reloads).  The host launches both; the largest window, found
 // while the block maxima are built, decides which one returns at once.
 #include <algorithm>
+#include <mutex>
 
 #include "common.hpp"
 
@@ -568,36 +569,51 @@ __global__ __launch_bounds__(64 * kWaves) void greedy_run(
 
 using namespace siting;
 
-static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+static constexpr size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Workspace layout of n candidates: key[n] u64, fresh[n] i32, block maxima
+// bmax[nb] u64 and their stamps bfr[nb] i32, the largest window's words u32.
+static constexpr size_t greedy_ws_bytes(int64_t n)
+{
+    return align256((size_t)n * 8) + align256((size_t)n * 4) +
+           align256((size_t)((n + kGreedyBlock - 1) / kGreedyBlock) * 8) +
+           align256((size_t)((n + kGreedyBlock - 1) / kGreedyBlock) * 4) + align256(4);
+}
+
+// The allocation-free entry point keeps its workspace in this array (one
+// copy per device, held until the process ends).  Host code must not pass
+// the array's name to a kernel: it is a host-side stand-in, and the device
+// address comes from hipGetSymbolAddress (noalloc_scratch below).
+constexpr int64_t kNoAllocMaxN = SITING_GREEDY_NOALLOC_MAX_N;
+constexpr size_t kNoAllocBytes = greedy_ws_bytes(kNoAllocMaxN);
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 
 extern "C" size_t siting_greedy_workspace_size(int64_t n)
 {
     if (n < 0)
         return 0;
-    const size_t nb = (size_t)((n + kGreedyBlock - 1) / kGreedyBlock);
-    return align256((size_t)n * 8) + align256((size_t)n * 4) + align256(nb * 8) + align256(nb * 4) +
-           align256(4);
+    return greedy_ws_bytes(n);
 }
 
-extern "C" int siting_greedy(const uint64_t *bitmaps, const int64_t *offsets,
-                             const siting_observer *obs, int64_t n, int64_t nrows, int64_t ncols,
-                             int32_t max_obs, int64_t target_cells, uint64_t *cumulative,
-                             int64_t *selected, int64_t *gains, int32_t *nselected, void *ws,
-                             size_t ws_bytes, void *stream)
+// Argument validation shared by both entry points (host only); SITING_OK or
+// an error code.
+static int greedy_check(const char *fn, const uint64_t *bitmaps, const int64_t *offsets,
+                        const siting_observer *obs, int64_t n, int64_t nrows, int64_t ncols,
+                        int32_t max_obs, const uint64_t *cumulative, const int64_t *selected,
+                        const int64_t *gains, const int32_t *nselected)
 {
-    clear_error();
-    const char *fn = "siting_greedy";
     SITING_REQUIRE(n >= 1 && n < 0xFFFFFFFFll, "%s: n must be in 1..2^32-2", fn);
     SITING_REQUIRE(nrows >= 1 && ncols >= 1, "%s: empty terrain", fn);
     SITING_REQUIRE(max_obs >= 0, "%s: max_obs < 0", fn);
     SITING_REQUIRE(bitmaps && offsets && obs && cumulative && nselected,
                    "%s: NULL device pointer", fn);
     SITING_REQUIRE(max_obs == 0 || (selected && gains), "%s: NULL selected/gains", fn);
-    const size_t need = siting_greedy_workspace_size(n);
-    if (ws == nullptr || ws_bytes < need) {
-        set_error("%s: workspace of %zu bytes needed", fn, need);
-        return SITING_E_WORKSPACE;
-    }
+    return SITING_OK;
+}
+
+// The candidate count the block maxima in LDS allow (asks the device).
+static int greedy_limits(const char *fn, int64_t n)
+{
     const int64_t nblocks = (n + kGreedyBlock - 1) / kGreedyBlock;
     const int lds_max = std::min(
         kernel_max_dynamic_lds(reinterpret_cast<const void *>(&greedy_run<1>)),
@@ -606,6 +622,18 @@ extern "C" int siting_greedy(const uint64_t *bitmaps, const int64_t *offsets,
         set_error("%s: %lld candidates exceed the supported maximum", fn, (long long)n);
         return SITING_E_UNSUPPORTED;
     }
+    return SITING_OK;
+}
+
+// Enqueues the rounds on `ws` (greedy_ws_bytes(n) bytes of device memory;
+// every part is written before it is read, so it needs no clearing).
+static int greedy_launch(const uint64_t *bitmaps, const int64_t *offsets,
+                         const siting_observer *obs, int64_t n, int64_t nrows, int64_t ncols,
+                         int32_t max_obs, int64_t target_cells, uint64_t *cumulative,
+                         int64_t *selected, int64_t *gains, int32_t *nselected, void *ws,
+                         void *stream)
+{
+    const int64_t nblocks = (n + kGreedyBlock - 1) / kGreedyBlock;
     char *wsb = reinterpret_cast<char *>(ws);
     uint64_t *key = reinterpret_cast<uint64_t *>(wsb);
     wsb += align256((size_t)n * 8);
@@ -644,4 +672,84 @@ extern "C" int siting_greedy(const uint64_t *bitmaps, const int64_t *offsets,
                        target_cells, cumulative, selected, gains, nselected, key, fresh, bmax_g,
                        bfr_g, maxwords);
     return check_launch("greedy_run");
+}
+
+extern "C" int siting_greedy(const uint64_t *bitmaps, const int64_t *offsets,
+                             const siting_observer *obs, int64_t n, int64_t nrows, int64_t ncols,
+                             int32_t max_obs, int64_t target_cells, uint64_t *cumulative,
+                             int64_t *selected, int64_t *gains, int32_t *nselected, void *ws,
+                             size_t ws_bytes, void *stream)
+{
+    clear_error();
+    const char *fn = "siting_greedy";
+    int rc = greedy_check(fn, bitmaps, offsets, obs, n, nrows, ncols, max_obs, cumulative,
+                          selected, gains, nselected);
+    if (rc != SITING_OK)
+        return rc;
+    const size_t need = greedy_ws_bytes(n);
+    if (ws == nullptr || ws_bytes < need) {
+        set_error("%s: workspace of %zu bytes needed", fn, need);
+        return SITING_E_WORKSPACE;
+    }
+    if ((rc = greedy_limits(fn, n)) != SITING_OK)
+        return rc;
+    return greedy_launch(bitmaps, offsets, obs, n, nrows, ncols, max_obs, target_cells,
+                         cumulative, selected, gains, nselected, ws, stream);
+}
+
+// Device address of `scratch` on the current device, looked up once per
+// device (each device holds its own copy of the array at its own address).
+static int noalloc_scratch(const char *fn, void **out)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        set_error("%s: hipGetDevice failed: %s", fn, hipGetErrorString(e));
+        return SITING_E_HIP;
+    }
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("%s: device %d beyond the supported %d", fn, dev, kMaxDevices);
+        return SITING_E_UNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    if (addr[dev] == nullptr) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr) {
+            set_error("%s: hipGetSymbolAddress(scratch) failed: %s", fn, hipGetErrorString(e));
+            return SITING_E_HIP;
+        }
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return SITING_OK;
+}
+
+extern "C" int siting_greedy_noalloc(const uint64_t *bitmaps, const int64_t *offsets,
+                                     const siting_observer *obs, int64_t n, int64_t nrows,
+                                     int64_t ncols, int32_t max_obs, int64_t target_cells,
+                                     uint64_t *cumulative, int64_t *selected, int64_t *gains,
+                                     int32_t *nselected, void *stream)
+{
+    clear_error();
+    const char *fn = "siting_greedy_noalloc";
+    int rc = greedy_check(fn, bitmaps, offsets, obs, n, nrows, ncols, max_obs, cumulative,
+                          selected, gains, nselected);
+    if (rc != SITING_OK)
+        return rc;
+    if (n > kNoAllocMaxN) {
+        set_error("%s: %lld candidates above the maximum %lld of the static workspace", fn,
+                  (long long)n, (long long)kNoAllocMaxN);
+        return SITING_E_UNSUPPORTED;
+    }
+    if ((rc = greedy_limits(fn, n)) != SITING_OK)
+        return rc;
+    void *ws = nullptr;
+    if ((rc = noalloc_scratch(fn, &ws)) != SITING_OK)
+        return rc;
+    return greedy_launch(bitmaps, offsets, obs, n, nrows, ncols, max_obs, target_cells,
+                         cumulative, selected, gains, nselected, ws, stream);
 }

@@ -56,6 +56,15 @@ def test_validation_errors_before_launch():
     assert lib.siting_greedy(fake, fake, fake, 0, 10, 10, 3, 100, fake, fake, fake, fake,
                              fake, 1 << 20, None) == -1
     assert lib.siting_greedy_workspace_size(100) >= 100 * 12
+    # allocation-free greedy: the same argument checks, and a candidate count
+    # above its static workspace is rejected before anything is enqueued
+    assert lib.siting_greedy_noalloc(fake, fake, fake, 0, 10, 10, 3, 100, fake, fake, fake,
+                                     fake, None) == -1
+    assert lib.siting_greedy_noalloc(fake, fake, fake, 5, 10, 10, 3, 100, fake, None, None,
+                                     fake, None) == -1
+    assert lib.siting_greedy_noalloc(fake, fake, fake, L.SITING_GREEDY_NOALLOC_MAX_N + 1, 10,
+                                     10, 3, 100, fake, fake, fake, fake, None) == -2
+    assert "maximum" in L.last_error()
     # visibility index: negative count, NULL pointers; nothing to do for n = 0
     assert lib.siting_visibility_index(fake, fake, -1, fake, None) == -1
     assert lib.siting_visibility_index(None, fake, 5, fake, None) == -1
