@@ -401,18 +401,65 @@ def test_pipeline_plain_1000_end_to_end(S, orc):
     assert res.coverage_cells == sum(bin(int(v)).count("1") for v in cum.ravel())
 
 
-def test_lowered_accuracy_scoring(S, orc):
-    # siting on degraded terrains, scored on the full one: the exact run's
-    # own choice scores exactly its coverage; degraded runs score a valid area
+def _oracle_site_positions(orc, z, cfg):
+    """The oracle's chain VIX -> FINDMAX -> VIEWSHED -> greedy SITE on terrain
+    z (host int16): the chosen posts' (x, y)."""
+    from paper_2006_16783_amd import pipeline as P
+    nr, nc = z.shape
+    cnt = orc.vix(z, cfg.roi, cfg.h_t, cfg.h_r, cfg.K, cfg.vix_seed)
+    cand = orc.findmax(cnt, z, cfg.grid, cfg.grid, cfg.k)
+    cand = cand[cand >= 0]
+    obs = orc.observers(cand % nc, cand // nc, cfg.roi, cfg.h_t, cfg.h_r)
+    bm, off = orc.viewshed(z, obs)
+    sel, _, _, _ = orc.greedy(bm, off, obs, nr, nc, cfg.max_obs,
+                              P.target_cells(cfg.target_frac, nr, nc), lazy=True)
+    return obs["x"][sel].astype(np.int64), obs["y"][sel].astype(np.int64)
+
+
+def _oracle_union(orc, z, xs, ys, cfg):
+    """Cells of terrain z seen by observers at (xs, ys): the OR of their
+    oracle viewsheds, counted."""
+    nr, nc = z.shape
+    obs = orc.observers(xs, ys, cfg.roi, cfg.h_t, cfg.h_r)
+    bm, off = orc.viewshed(z, obs)
+    C = np.zeros((nr, (nc + 63) // 64), np.uint64)
+    for i, o in enumerate(obs):
+        R, x, y = int(o["roi"]), int(o["x"]), int(o["y"])
+        ylo, yhi = max(0, y - R), min(nr - 1, y + R)
+        w0, w1 = max(0, x - R) >> 6, min(nc - 1, x + R) >> 6
+        C[ylo:yhi + 1, w0:w1 + 1] |= bm[off[i]:off[i + 1]].reshape(yhi - ylo + 1, w1 - w0 + 1)
+    return int(np.bitwise_count(C).sum())
+
+
+@pytest.mark.parametrize("q,f", [(1, 1), (10, 1), (50, 1), (1, 2), (1, 4)])
+def test_lowered_accuracy_against_oracle(S, orc, q, f):
+    # the 1000^2 workload (ROI 100, h 10/10, K 10, 10x10 blocks x 10, SITE to
+    # 100) sited on a degraded terrain -- elevations quantised to q m, or
+    # every f-th post with the ROI divided by f -- and scored on the full
+    # terrain: the chosen posts and the union area of their viewsheds there
+    # equal the oracle's chain on the same degraded array
+    import dataclasses
     from paper_2006_16783_amd import accuracy as A
     from paper_2006_16783_amd import pipeline as P
-    cfg = P.SitingConfig("acc", 400, 2.4, 900, 3, 40, 10, 10, 10, 8, 5, 30, 1.0)
-    z = torch.from_numpy(_terrain(400, 2.4, 900, 3)).cuda()
-    xs, ys, _, res = A.site_degraded(z, cfg)
-    assert A.union_area(z, xs, ys, cfg) == res.coverage_cells
-    for q, f in [(20, 1), (1, 2)]:
-        xs, ys, _, r = A.site_degraded(z, cfg, q, f)
-        assert len(xs) == len(r.selected) > 0
-        assert (xs % f == 0).all() and (xs < 400).all() and (ys < 400).all()
-        area = A.union_area(z, xs, ys, cfg)
-        assert 0 < area <= 400 * 400
+    _say("accuracy", q, f)
+    cfg = P.CONFIGS["plain_1000"]
+    z = _terrain(cfg.n, cfg.beta, cfg.zmax, cfg.seed)
+    zd = torch.from_numpy(z).cuda()
+    xs, ys, _, res = A.site_degraded(zd, cfg, q, f)
+    area = A.union_area(zd, xs, ys, cfg)
+    # the oracle on the same degraded terrain (host arithmetic on the array)
+    zq = (z // q * q).astype(np.int16) if q > 1 else z
+    c = cfg
+    if f > 1:
+        zq = np.ascontiguousarray(zq[::f, ::f])
+        c = dataclasses.replace(cfg, n=zq.shape[0], roi=max(1, cfg.roi // f),
+                                grid=min(cfg.grid, zq.shape[0]))
+    oxs, oys = _oracle_site_positions(orc, zq, c)
+    assert len(oxs) == len(xs) > 0
+    assert (oxs * f == xs).all() and (oys * f == ys).all()
+    want = _oracle_union(orc, z, xs, ys, cfg)
+    assert area == want
+    if (q, f) == (1, 1):
+        # the exact run's own choice scores exactly its coverage
+        assert area == res.coverage_cells
+    _say("accuracy", q, f, "observers", len(xs), "area", area)
