@@ -62,9 +62,9 @@ def _load():
         lib.or_disk_cells.argtypes = [P, i64, i64]
         lib.or_disk_cells.restype = i64
         lib.or_viewshed_count.argtypes = [P, i64, i64, i64, P, i64, P, P]
-        lib.or_greedy.argtypes = [P, P, P, i64, i64, i64, i32, i64, P, P, P]
+        lib.or_greedy.argtypes = [P, P, P, i64, i64, i64, i32, i64, P, P, P, i32]
         lib.or_greedy.restype = i32
-        lib.or_greedy_lazy.argtypes = [P, P, P, i64, i64, i64, i32, i64, P, P, P, P]
+        lib.or_greedy_lazy.argtypes = [P, P, P, i64, i64, i64, i32, i64, P, P, P, P, i32]
         lib.or_greedy_lazy.restype = i32
         lib.or_num_threads.restype = i32
         lib.or_set_threads.argtypes = [i32]
@@ -262,9 +262,12 @@ def disk_cells(ob, nrows, ncols) -> int:
     return int(_load().or_disk_cells(_ptr(ob), int(nrows), int(ncols)))
 
 
-def greedy(bitmaps, offsets, obs, nrows, ncols, max_obs, target_cells, lazy=False):
+def greedy(bitmaps, offsets, obs, nrows, ncols, max_obs, target_cells, lazy=False,
+           intervisible=False):
     """Greedy siting: stage Site (lazy=True uses the stage's optimisation
-    that gains never grow).  Returns (selected, gains, cumulative[, evals])."""
+    that gains never grow).  intervisible=True: after the first pick only
+    candidates whose post lies in the cumulative viewshed compete.  Returns
+    (selected, gains, cumulative[, evals])."""
     obs = np.ascontiguousarray(obs, OBSERVER_DTYPE)
     bitmaps = np.ascontiguousarray(bitmaps, np.uint64)
     offsets = np.ascontiguousarray(offsets, np.int64)
@@ -277,10 +280,11 @@ def greedy(bitmaps, offsets, obs, nrows, ncols, max_obs, target_cells, lazy=Fals
         ev = np.zeros(1, np.int64)
         t = lib.or_greedy_lazy(_ptr(bitmaps), _ptr(offsets), _ptr(obs), len(obs), int(nrows),
                                int(ncols), int(max_obs), int(target_cells), _ptr(cum),
-                               _ptr(sel), _ptr(gains), _ptr(ev))
+                               _ptr(sel), _ptr(gains), _ptr(ev), int(bool(intervisible)))
         return sel[:t].copy(), gains[:t].copy(), cum, int(ev[0])
     t = lib.or_greedy(_ptr(bitmaps), _ptr(offsets), _ptr(obs), len(obs), int(nrows), int(ncols),
-                      int(max_obs), int(target_cells), _ptr(cum), _ptr(sel), _ptr(gains))
+                      int(max_obs), int(target_cells), _ptr(cum), _ptr(sel), _ptr(gains),
+                      int(bool(intervisible)))
     return sel[:t].copy(), gains[:t].copy(), cum
 
 

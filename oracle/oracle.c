@@ -553,9 +553,27 @@ static void unite(const uint64_t *bitmaps, const int64_t *offsets, const or_obse
             C[y * W + w0 + w] |= v[(y - ylo) * nw + w];
 }
 
+/* Intervisibility (a constraint the paper names among the variants of the
+ * problem: transmitters must be visible from other transmitters).  Read as:
+ * after the first selection, a candidate may be selected only if its own
+ * post lies in the cumulative viewshed of those already selected, i.e. it
+ * is visible from at least one of them; the first selection is free.  A
+ * candidate outside the terrain is never eligible after the first round.  */
+static int eligible(const or_observer *o, int64_t nrows, int64_t ncols, const uint64_t *C,
+                    int64_t W, int32_t t)
+{
+    if (t == 0)
+        return 1;
+    if (o->x < 0 || o->x >= ncols || o->y < 0 || o->y >= nrows)
+        return 0;
+    return (int)((C[(int64_t)o->y * W + (o->x >> 6)] >> (o->x & 63)) & 1u);
+}
+
+/* inter != 0: only eligible candidates (above) compete in each round; the
+ * run stops when no eligible candidate gains anything.                    */
 int32_t or_greedy(const uint64_t *bitmaps, const int64_t *offsets, const or_observer *obs,
                   int64_t n, int64_t nrows, int64_t ncols, int32_t max_obs, int64_t target_cells,
-                  uint64_t *cumulative, int64_t *selected, int64_t *gains)
+                  uint64_t *cumulative, int64_t *selected, int64_t *gains, int32_t inter)
 {
     int64_t W = (ncols + 63) / 64;
     memset(cumulative, 0, (size_t)(nrows * W) * sizeof(uint64_t));
@@ -568,7 +586,8 @@ int32_t or_greedy(const uint64_t *bitmaps, const int64_t *offsets, const or_obse
             g[i] = gain_of(bitmaps, offsets, &obs[i], i, nrows, ncols, cumulative, W);
         int64_t best = -1;
         for (int64_t i = 0; i < n; i++)
-            if (best < 0 || g[i] > g[best])
+            if ((!inter || eligible(&obs[i], nrows, ncols, cumulative, W, t)) &&
+                (best < 0 || g[i] > g[best]))
                 best = i;
         if (best < 0 || g[best] == 0)
             break;
@@ -587,11 +606,11 @@ int32_t or_greedy(const uint64_t *bitmaps, const int64_t *offsets, const or_obse
  * accelerated greedy): the stale gains are upper bounds; the candidate with
  * the largest bound (ties to the smallest index) is re-evaluated, and is
  * taken once its bound is fresh for the current round.  Same tie rule, so
- * the same selection as or_greedy.                                        */
+ * the same selection as or_greedy (with or without intervisibility).      */
 int32_t or_greedy_lazy(const uint64_t *bitmaps, const int64_t *offsets, const or_observer *obs,
                        int64_t n, int64_t nrows, int64_t ncols, int32_t max_obs,
                        int64_t target_cells, uint64_t *cumulative, int64_t *selected,
-                       int64_t *gains, int64_t *n_evals)
+                       int64_t *gains, int64_t *n_evals, int32_t inter)
 {
     int64_t W = (ncols + 63) / 64;
     memset(cumulative, 0, (size_t)(nrows * W) * sizeof(uint64_t));
@@ -604,10 +623,15 @@ int32_t or_greedy_lazy(const uint64_t *bitmaps, const int64_t *offsets, const or
     int64_t evals = n, covered = 0;
     int32_t t = 0;
     while (t < max_obs && covered < target_cells && n > 0) {
-        int64_t best = 0;
-        for (int64_t i = 1; i < n; i++)
-            if (bound[i] > bound[best])
+        /* with intervisibility, the bounds of the eligible candidates only
+         * (a bound stays valid while a candidate waits to become eligible) */
+        int64_t best = -1;
+        for (int64_t i = 0; i < n; i++)
+            if ((!inter || eligible(&obs[i], nrows, ncols, cumulative, W, t)) &&
+                (best < 0 || bound[i] > bound[best]))
                 best = i;
+        if (best < 0)
+            break;
         if (fresh[best] != t) {
             bound[best] = gain_of(bitmaps, offsets, &obs[best], best, nrows, ncols, cumulative, W);
             fresh[best] = t;

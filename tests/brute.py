@@ -127,6 +127,27 @@ def greedy_sets(sets, max_obs, target):
     return sel, gains, cov
 
 
+def greedy_sets_intervisible(sets, posts, max_obs, target):
+    """The same greedy with intervisibility: after the first pick, only
+    candidates whose post (x, y) is already covered compete."""
+    cov = set()
+    sel, gains = [], []
+    while len(sel) < max_obs and len(cov) < target:
+        best, bg = -1, -1
+        for i, s in enumerate(sets):
+            if sel and posts[i] not in cov:
+                continue
+            g = len(s - cov)
+            if g > bg:
+                best, bg = i, g
+        if bg <= 0:
+            break
+        sel.append(best)
+        gains.append(bg)
+        cov |= sets[best]
+    return sel, gains, cov
+
+
 def best_cover(sets, m):
     """Exhaustive optimum coverage with m sets (tiny inputs only)."""
     best = 0

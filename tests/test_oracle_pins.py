@@ -503,6 +503,48 @@ def test_greedy_stop_rules(orc):
     assert len(sel2) == 2
 
 
+def test_greedy_intervisible_brute_and_lazy(orc):
+    # intervisibility: after the first pick a candidate competes only if its
+    # post is covered; the oracle (plain and lazy) against greedy over Python
+    # sets with that rule, and every later pick lies in the union of the
+    # viewsheds chosen before it
+    for seed in range(5):
+        z = fbm(90, 2.4, 500, 40 + seed)
+        obs = uniform_observers(90, 90, 40, 10 + seed, roi=(4, 22), height=(1, 12))
+        bm, off, sets = _sets_from(orc, z, obs)
+        posts = [(int(o["x"]), int(o["y"])) for o in obs]
+        target = int(math.ceil(0.95 * 90 * 90))
+        sel, gains, cum = orc.greedy(bm, off, obs, 90, 90, 30, target, intervisible=True)
+        bsel, bgains, bcov = brute.greedy_sets_intervisible(sets, posts, 30, target)
+        assert sel.tolist() == bsel and gains.tolist() == bgains
+        lsel, lgains, lcum, _ = orc.greedy(bm, off, obs, 90, 90, 30, target, lazy=True,
+                                          intervisible=True)
+        assert lsel.tolist() == bsel and lgains.tolist() == bgains and (lcum == cum).all()
+        seen = set()
+        for t, i in enumerate(bsel):
+            assert t == 0 or posts[i] in seen
+            seen |= sets[i]
+        pop = sum(bin(int(v)).count("1") for v in cum.ravel())
+        assert pop == int(gains.sum()) == len(bcov)
+
+
+def test_greedy_intervisible_chain_on_flat_terrain(orc):
+    # flat terrain: every viewshed is its whole disk.  A (R 20) is picked
+    # first; B lies in A's disk, C only in B's, D (R 15) far from all: with
+    # intervisibility the picks are A, B, C and D never becomes eligible;
+    # without it D's larger disk is picked second
+    z = np.zeros((100, 100), np.int16)
+    obs = orc.observers([50, 65, 74, 20], [50, 50, 50, 20], [20, 10, 10, 15], 5, 5)
+    bm, off = orc.viewshed(z, obs)
+    sel, gains, _ = orc.greedy(bm, off, obs, 100, 100, 10, 10**9, intervisible=True)
+    assert sel.tolist() == [0, 1, 2]
+    disk = lambda R: sum(1 for dx in range(-R, R + 1) for dy in range(-R, R + 1)
+                         if dx * dx + dy * dy <= R * R)
+    assert gains[0] == disk(20)
+    free, fgains, _ = orc.greedy(bm, off, obs, 100, 100, 10, 10**9)
+    assert free.tolist()[:2] == [0, 3] and fgains[1] == disk(15)
+
+
 def test_greedy_approximation_bound(orc):
     # greedy >= (1 - 1/e) of the exhaustive optimum (Nemhauser-Wolsey-Fisher)
     for seed in range(3):
