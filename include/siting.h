@@ -269,12 +269,30 @@ int siting_autotune_candidates(int32_t rmax, siting_schedule *out_host, int32_t 
  *   selected, gains : out (device) int64[max_obs]; entries past *nselected
  *                     are left untouched
  *   nselected  : out (device) int32, number selected
- *   ws, ws_bytes : workspace of siting_greedy_workspace_size(n) bytes */
+ *   ws, ws_bytes : workspace of siting_greedy_workspace_size(n) bytes (the
+ *                  size serves siting_greedy_intervisible as well) */
 size_t siting_greedy_workspace_size(int64_t n);
 int siting_greedy(const uint64_t *bitmaps, const int64_t *offsets, const siting_observer *obs,
                   int64_t n, int64_t nrows, int64_t ncols, int32_t max_obs, int64_t target_cells,
                   uint64_t *cumulative, int64_t *selected, int64_t *gains, int32_t *nselected,
                   void *ws, size_t ws_bytes, void *stream);
+
+/* The same selection under intervisibility, a constraint the paper names
+ * among the variants of the problem (transmitters required to be visible from
+ * other transmitters): the first pick is free; after it, a candidate competes
+ * only if its own post lies in the cumulative viewshed C, i.e. it is visible
+ * (as a receiver, h_r above the terrain) from at least one transmitter already
+ * chosen, so every transmitter after the first is seen by an earlier one.  A
+ * round takes the competing candidate with the largest gain (ties to the
+ * smallest index); the run also stops when no competing candidate gains
+ * anything.  A record with a position or roi out of range never competes
+ * after the first round.  Arguments, outputs and errors as siting_greedy;
+ * ws, ws_bytes: siting_greedy_workspace_size(n) bytes. */
+int siting_greedy_intervisible(const uint64_t *bitmaps, const int64_t *offsets,
+                               const siting_observer *obs, int64_t n, int64_t nrows,
+                               int64_t ncols, int32_t max_obs, int64_t target_cells,
+                               uint64_t *cumulative, int64_t *selected, int64_t *gains,
+                               int32_t *nselected, void *ws, size_t ws_bytes, void *stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same

@@ -49,6 +49,16 @@ constexpr int kGreedyWaves = GREEDY_WAVES;  // wavefronts for windows above one 
 // popcount totals of a window: at most (2*16383+1)^2 < 2^31 bits
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) { return wave_sum_u32((uint32_t)v); }
 
+// A load served by L2, not by the CU's L1: for values this workgroup stored
+// earlier in the same launch, where a stale L1 copy would be wrong (with
+// intervisibility a key can grow back from 0; a plain key only shrinks, so a
+// stale read of it is still an upper bound).
+template <typename T>
+__device__ __forceinline__ T load_l2(const T *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 struct Win {
     int64_t ylo, w0;
     int rows, nw;
@@ -309,14 +319,27 @@ struct BigRound {
 // other wavefronts wait at a barrier and join only rounds whose window is
 // larger than one batch (64 * kGreedyWords words), each taking every
 // kWaves-th batch, so small windows pay no barrier at all.
-template <int kWaves>
+//
+// kInter (intervisibility): after the first pick only candidates whose post
+// lies in C compete.  Right after the first pick every other candidate whose
+// post C does not cover is parked: its key moves to pbound and becomes 0 (a
+// parked key never wins; a stale bound stays an upper bound while it waits),
+// and it joins a list of (index, position).  After each later pick, wavefront
+// 0 scans that list for parked candidates inside the new window whose post C
+// now covers and puts their bounds back (raising the block maxima, marked
+// stale).  Eligibility only grows, so each candidate parks at most once.
+// Both steps test a post against the window just taken, in the (read-only)
+// window bitmap: C was empty before the first pick, and a parked post was
+// not in C before the pick that may cover it.
+template <int kWaves, bool kInter>
 __global__ __launch_bounds__(64 * kWaves) void greedy_run(
     const uint64_t *__restrict__ bitmaps, const int64_t *__restrict__ offsets,
     const siting_observer *__restrict__ obs, int64_t n, int64_t nrows, int64_t ncols,
     int32_t max_obs, int64_t target, uint64_t *C, int64_t *__restrict__ selected,
     int64_t *__restrict__ gains, int32_t *__restrict__ nselected, uint64_t *key, int32_t *fresh,
     const uint64_t *__restrict__ bmax_g, const int32_t *__restrict__ bfr_g,
-    const uint32_t *__restrict__ maxwords)
+    const uint32_t *__restrict__ maxwords, uint64_t *__restrict__ pbound,
+    int32_t *__restrict__ plist_idx, int64_t *__restrict__ plist_xy)
 {
     // both instantiations are launched: one wavefront when every window fits
     // one batch, kWaves otherwise; the other returns at once
@@ -376,6 +399,8 @@ __global__ __launch_bounds__(64 * kWaves) void greedy_run(
     // ---- wavefront 0
     int32_t t = 0;
     int64_t covered = 0;
+    int64_t nparked = 0;  // entries of the parked list (kInter)
+    const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     // the next round's top is known when a round ends (the larger of the best
     // key outside the round's block and that block's new maximum): its record
     // and its block's keys are loaded then, while the next top selection runs
@@ -388,8 +413,13 @@ __global__ __launch_bounds__(64 * kWaves) void greedy_run(
 #pragma unroll
         for (int u = 0; u < kGreedyKeys; u++) {
             const int64_t j = (int64_t)b * kGreedyBlock + u * 64 + lane;
-            kk[u] = j < n && j != skip ? key[j] : 0;
-            ff[u] = j < n ? fresh[j] : 0;
+            if (kInter) {
+                kk[u] = j < n && j != skip ? load_l2(&key[j]) : 0;
+                ff[u] = j < n ? load_l2(&fresh[j]) : 0;
+            } else {
+                kk[u] = j < n && j != skip ? key[j] : 0;
+                ff[u] = j < n ? fresh[j] : 0;
+            }
         }
     };
     while (t < max_obs && covered < target) {
@@ -526,8 +556,98 @@ __global__ __launch_bounds__(64 * kWaves) void greedy_run(
         }
         if (big)
             __syncthreads();  // the helpers' ORs are in C
+        if (kInter && take) {
+            // is post (px, py) set in the window just taken?
+            const int64_t xlo = o.x - o.roi < 0 ? 0 : o.x - o.roi;
+            const int64_t xhi = o.x + o.roi > ncols - 1 ? ncols - 1 : o.x + o.roi;
+            const int64_t yhi = w.ylo + w.rows - 1;
+            auto in_window = [&](int64_t px, int64_t py) {
+                if (px < xlo || px > xhi || py < w.ylo || py > yhi)
+                    return false;
+                const uint64_t word = v[(py - w.ylo) * w.nw + ((px >> 6) - w.w0)];
+                return ((word >> (px & 63)) & 1ull) != 0;
+            };
+            // this round's stores (keys, stamps) complete before the reads below
+            __builtin_amdgcn_s_waitcnt(0);
+            if (t == 1) {
+                // park every candidate the first window does not cover, block
+                // by block (a block's 512 keys are 8 steps of the wavefront),
+                // and rebuild the block maxima from the registers
+                for (int b = 0; b < nblocks; b++) {
+                    uint64_t bv = 0;
+                    int32_t bf = 0;
+                    for (int u = 0; u < kGreedyKeys; u++) {
+                        const int64_t j = (int64_t)b * kGreedyBlock + u * 64 + lane;
+                        const bool inb = j < n;
+                        const int64_t jj = inb ? j : 0;
+                        // every lane loads (lanes past n reload candidate 0 and
+                        // discard it), so nothing below is assigned under a branch
+                        const siting_observer oj = obs[jj];
+                        uint64_t kj = load_l2(&key[jj]);
+                        const int32_t fj = load_l2(&fresh[jj]);
+                        const bool okj = inb && obs_ok(oj, nrows, ncols);
+                        const bool seen = okj && in_window(oj.x, oj.y);
+                        const bool out = inb && !seen;  // parked (or invalid): key 0
+                        const bool park = okj && !seen;  // invalid records never return
+                        if (out) {
+                            pbound[j] = kj;
+                            key[j] = 0;
+                        }
+                        kj = out || !inb ? 0 : kj;
+                        const int64_t xy = ((int64_t)oj.y << 32) | (uint32_t)oj.x;
+                        const uint64_t pm = __ballot(park);
+                        if (park) {
+                            const int64_t e = nparked + __popcll(pm & lt_mask);
+                            plist_idx[e] = (int32_t)j;
+                            plist_xy[e] = xy;
+                        }
+                        nparked += __popcll(pm);
+                        if (kj > bv) {
+                            bv = kj;
+                            bf = fj;
+                        }
+                    }
+                    const uint64_t m = wave_max_u64(bv);
+                    const uint64_t own = __ballot(bv == m && m != 0);
+                    const int32_t mf =
+                        __builtin_amdgcn_readlane(bf, own ? __ffsll((long long)own) - 1 : 0);
+                    if (lane == 0) {
+                        bmax[b] = m;
+                        bfr[b] = mf;
+                    }
+                }
+            } else {
+                // parked candidates whose post the window just taken covers
+                // become eligible again with their old bound
+                for (int64_t e0 = 0; e0 < nparked; e0 += 64) {
+                    const int64_t e = e0 + lane;
+                    if (e >= nparked)
+                        continue;
+                    const int64_t xy = load_l2(&plist_xy[e]);
+                    const int64_t px = (int64_t)(int32_t)(uint32_t)xy, py = xy >> 32;
+                    if (!in_window(px, py))
+                        continue;
+                    const int32_t j = load_l2(&plist_idx[e]);
+                    if (j < 0)
+                        continue;
+                    const uint64_t kj = load_l2(&pbound[j]);
+                    key[j] = kj;
+                    plist_idx[e] = -1;
+                    const int b = j / kGreedyBlock;
+                    const uint64_t old = atomicMax(reinterpret_cast<unsigned long long *>(&bmax[b]),
+                                                   (unsigned long long)kj);
+                    if (kj > old)
+                        bfr[b] = -1;  // the block's maximum is a stale bound now
+                }
+            }
+            // the keys and list entries stored above complete before the
+            // next round reads them
+            __builtin_amdgcn_s_waitcnt(0);
+        }
         // the next top: the best key outside block bi or bi's new maximum
-        {
+        if (kInter && take) {
+            pf_i = -1;  // keys of many blocks may have changed: no prefetch
+        } else {
             const uint64_t bnew = ki > bo ? ki : bo;
             const uint64_t nx = second > bnew ? second : bnew;
             const int64_t p = (int64_t)(0xFFFFFFFFull - (nx & 0xFFFFFFFFull));
@@ -572,12 +692,19 @@ using namespace siting;
 static constexpr size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // Workspace layout of n candidates: key[n] u64, fresh[n] i32, block maxima
-// bmax[nb] u64 and their stamps bfr[nb] i32, the largest window's words u32.
+// bmax[nb] u64 and their stamps bfr[nb] i32, the largest window's words u32;
+// with intervisibility also the parked bounds pbound[n] u64 and the parked
+// list (index i32, packed position i64) of up to n entries.
 static constexpr size_t greedy_ws_bytes(int64_t n)
 {
     return align256((size_t)n * 8) + align256((size_t)n * 4) +
            align256((size_t)((n + kGreedyBlock - 1) / kGreedyBlock) * 8) +
            align256((size_t)((n + kGreedyBlock - 1) / kGreedyBlock) * 4) + align256(4);
+}
+static constexpr size_t greedy_inter_ws_bytes(int64_t n)
+{
+    return greedy_ws_bytes(n) + align256((size_t)n * 8) + align256((size_t)n * 4) +
+           align256((size_t)n * 8);
 }
 
 // The allocation-free entry point keeps its workspace in this array (one
@@ -592,7 +719,7 @@ extern "C" size_t siting_greedy_workspace_size(int64_t n)
 {
     if (n < 0)
         return 0;
-    return greedy_ws_bytes(n);
+    return greedy_inter_ws_bytes(n);  // enough for both entry points
 }
 
 // Argument validation shared by both entry points (host only); SITING_OK or
@@ -616,8 +743,12 @@ static int greedy_limits(const char *fn, int64_t n)
 {
     const int64_t nblocks = (n + kGreedyBlock - 1) / kGreedyBlock;
     const int lds_max = std::min(
-        kernel_max_dynamic_lds(reinterpret_cast<const void *>(&greedy_run<1>)),
-        kernel_max_dynamic_lds(reinterpret_cast<const void *>(&greedy_run<kGreedyWaves>)));
+        std::min(kernel_max_dynamic_lds(reinterpret_cast<const void *>(&greedy_run<1, false>)),
+                 kernel_max_dynamic_lds(
+                     reinterpret_cast<const void *>(&greedy_run<kGreedyWaves, false>))),
+        std::min(kernel_max_dynamic_lds(reinterpret_cast<const void *>(&greedy_run<1, true>)),
+                 kernel_max_dynamic_lds(
+                     reinterpret_cast<const void *>(&greedy_run<kGreedyWaves, true>))));
     if (nblocks > kGreedyMaxBlocks || nblocks * 12 > lds_max) {
         set_error("%s: %lld candidates exceed the supported maximum", fn, (long long)n);
         return SITING_E_UNSUPPORTED;
@@ -625,13 +756,14 @@ static int greedy_limits(const char *fn, int64_t n)
     return SITING_OK;
 }
 
-// Enqueues the rounds on `ws` (greedy_ws_bytes(n) bytes of device memory;
-// every part is written before it is read, so it needs no clearing).
+// Enqueues the rounds on `ws` (greedy_ws_bytes(n) bytes of device memory,
+// greedy_inter_ws_bytes(n) with intervisibility; every part is written
+// before it is read, so it needs no clearing).
 static int greedy_launch(const uint64_t *bitmaps, const int64_t *offsets,
                          const siting_observer *obs, int64_t n, int64_t nrows, int64_t ncols,
                          int32_t max_obs, int64_t target_cells, uint64_t *cumulative,
                          int64_t *selected, int64_t *gains, int32_t *nselected, void *ws,
-                         void *stream)
+                         void *stream, bool inter)
 {
     const int64_t nblocks = (n + kGreedyBlock - 1) / kGreedyBlock;
     char *wsb = reinterpret_cast<char *>(ws);
@@ -644,6 +776,17 @@ static int greedy_launch(const uint64_t *bitmaps, const int64_t *offsets,
     int32_t *bfr_g = reinterpret_cast<int32_t *>(wsb);
     wsb += align256((size_t)nblocks * 4);
     uint32_t *maxwords = reinterpret_cast<uint32_t *>(wsb);
+    wsb += align256(4);
+    uint64_t *pbound = nullptr;
+    int32_t *plist_idx = nullptr;
+    int64_t *plist_xy = nullptr;
+    if (inter) {
+        pbound = reinterpret_cast<uint64_t *>(wsb);
+        wsb += align256((size_t)n * 8);
+        plist_idx = reinterpret_cast<int32_t *>(wsb);
+        wsb += align256((size_t)n * 4);
+        plist_xy = reinterpret_cast<int64_t *>(wsb);
+    }
     hipStream_t s = as_stream(stream);
     const int64_t W = (ncols + 63) / 64;
     const int64_t cwords = nrows * W;
@@ -662,15 +805,22 @@ static int greedy_launch(const uint64_t *bitmaps, const int64_t *offsets,
     if ((rc = check_launch("greedy_blocks")) != SITING_OK)
         return rc;
     // one of the two returns at once (the largest window decides)
-    hipLaunchKernelGGL(greedy_run<1>, dim3(1), dim3(64), (size_t)nblocks * 12, s, bitmaps, offsets,
-                       obs, n, nrows, ncols, max_obs, target_cells, cumulative, selected, gains,
-                       nselected, key, fresh, bmax_g, bfr_g, maxwords);
+#define GREEDY_RUN(WAVES, INTER)                                                                \
+    hipLaunchKernelGGL((greedy_run<WAVES, INTER>), dim3(1), dim3(64 * (WAVES)),                \
+                       (size_t)nblocks * 12, s, bitmaps, offsets, obs, n, nrows, ncols, max_obs, \
+                       target_cells, cumulative, selected, gains, nselected, key, fresh, bmax_g, \
+                       bfr_g, maxwords, pbound, plist_idx, plist_xy)
+    if (inter)
+        GREEDY_RUN(1, true);
+    else
+        GREEDY_RUN(1, false);
     if ((rc = check_launch("greedy_run")) != SITING_OK)
         return rc;
-    hipLaunchKernelGGL(greedy_run<kGreedyWaves>, dim3(1), dim3(64 * kGreedyWaves),
-                       (size_t)nblocks * 12, s, bitmaps, offsets, obs, n, nrows, ncols, max_obs,
-                       target_cells, cumulative, selected, gains, nselected, key, fresh, bmax_g,
-                       bfr_g, maxwords);
+    if (inter)
+        GREEDY_RUN(kGreedyWaves, true);
+    else
+        GREEDY_RUN(kGreedyWaves, false);
+#undef GREEDY_RUN
     return check_launch("greedy_run");
 }
 
@@ -694,7 +844,31 @@ extern "C" int siting_greedy(const uint64_t *bitmaps, const int64_t *offsets,
     if ((rc = greedy_limits(fn, n)) != SITING_OK)
         return rc;
     return greedy_launch(bitmaps, offsets, obs, n, nrows, ncols, max_obs, target_cells,
-                         cumulative, selected, gains, nselected, ws, stream);
+                         cumulative, selected, gains, nselected, ws, stream, false);
+}
+
+extern "C" int siting_greedy_intervisible(const uint64_t *bitmaps, const int64_t *offsets,
+                                          const siting_observer *obs, int64_t n, int64_t nrows,
+                                          int64_t ncols, int32_t max_obs, int64_t target_cells,
+                                          uint64_t *cumulative, int64_t *selected,
+                                          int64_t *gains, int32_t *nselected, void *ws,
+                                          size_t ws_bytes, void *stream)
+{
+    clear_error();
+    const char *fn = "siting_greedy_intervisible";
+    int rc = greedy_check(fn, bitmaps, offsets, obs, n, nrows, ncols, max_obs, cumulative,
+                          selected, gains, nselected);
+    if (rc != SITING_OK)
+        return rc;
+    const size_t need = greedy_inter_ws_bytes(n);
+    if (ws == nullptr || ws_bytes < need) {
+        set_error("%s: workspace of %zu bytes needed", fn, need);
+        return SITING_E_WORKSPACE;
+    }
+    if ((rc = greedy_limits(fn, n)) != SITING_OK)
+        return rc;
+    return greedy_launch(bitmaps, offsets, obs, n, nrows, ncols, max_obs, target_cells,
+                         cumulative, selected, gains, nselected, ws, stream, true);
 }
 
 // Device address of `scratch` on the current device, looked up once per
@@ -751,5 +925,5 @@ extern "C" int siting_greedy_noalloc(const uint64_t *bitmaps, const int64_t *off
     if ((rc = noalloc_scratch(fn, &ws)) != SITING_OK)
         return rc;
     return greedy_launch(bitmaps, offsets, obs, n, nrows, ncols, max_obs, target_cells,
-                         cumulative, selected, gains, nselected, ws, stream);
+                         cumulative, selected, gains, nselected, ws, stream, false);
 }

@@ -56,6 +56,12 @@ def test_validation_errors_before_launch():
     assert lib.siting_greedy(fake, fake, fake, 0, 10, 10, 3, 100, fake, fake, fake, fake,
                              fake, 1 << 20, None) == -1
     assert lib.siting_greedy_workspace_size(100) >= 100 * 12
+    # intervisible greedy: same checks, the larger workspace
+    assert lib.siting_greedy_intervisible(fake, fake, fake, 5, 10, 10, 3, 100, fake, fake, fake,
+                                          fake, fake, 8, None) == -4
+    assert lib.siting_greedy_intervisible(fake, fake, fake, 0, 10, 10, 3, 100, fake, fake, fake,
+                                          fake, fake, 1 << 20, None) == -1
+    assert lib.siting_greedy_workspace_size(100) >= 100 * 32
     # allocation-free greedy: the same argument checks, and a candidate count
     # above its static workspace is rejected before anything is enqueued
     assert lib.siting_greedy_noalloc(fake, fake, fake, 0, 10, 10, 3, 100, fake, fake, fake,

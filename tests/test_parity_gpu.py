@@ -320,6 +320,47 @@ def test_greedy_large_windows(S, orc, seed, n_obs, roi):
     assert (_u64(cum).reshape(-1) == wcum.reshape(-1)).all()
 
 
+@pytest.mark.parametrize("seed,nr,nc,n_obs,roi,max_obs", [
+    (61, 500, 500, 600, (20, 90), 150),    # one-wavefront rounds
+    (62, 900, 870, 300, (100, 400), 80),   # windows above 1024 words: four wavefronts
+    (63, 400, 400, 2000, (5, 30), 400),    # many small windows; picks stop when none is seen
+])
+def test_greedy_intervisible_parity(S, orc, seed, nr, nc, n_obs, roi, max_obs):
+    # intervisibility: after the first pick only candidates whose post lies in
+    # the cumulative viewshed compete; selection, gains and cumulative
+    # viewshed equal the oracle's on its own bitmaps
+    _say("greedy intervisible", seed, nr, nc, n_obs, roi, max_obs)
+    from synth import uniform_observers
+    z = _terrain(nr, 2.4, 1500, seed, ncols=nc)
+    obs = uniform_observers(nr, nc, n_obs, seed, roi=roi, height=(5, 40))
+    bm_h, off = orc.viewshed(z, obs)
+    wsel, wgain, wcum, _ = orc.greedy(bm_h, off, obs, nr, nc, max_obs, nr * nc, lazy=True,
+                                      intervisible=True)
+    bm = torch.from_numpy(bm_h.view(np.int64)).cuda()
+    sel, gains, nsel, cum = S.siting_greedy(bm, torch.from_numpy(off).cuda(),
+                                            S.observers_to_device(obs), nr, nc, max_obs, nr * nc,
+                                            intervisible=True)
+    m = int(nsel.item())
+    _say("picks", m, "of", max_obs)
+    assert m == len(wsel)
+    assert (sel[:m].cpu().numpy() == wsel).all()
+    assert (gains[:m].cpu().numpy() == wgain).all()
+    assert (_u64(cum).reshape(-1) == wcum.reshape(-1)).all()
+
+
+def test_greedy_intervisible_chain_on_flat_terrain(S, orc):
+    # flat terrain, every viewshed its disk: A first, then B (in A's disk),
+    # then C (only in B's); D far away never becomes eligible
+    z = np.zeros((100, 100), np.int16)
+    obs = orc.observers([50, 65, 74, 20], [50, 50, 50, 20], [20, 10, 10, 15], 5, 5)
+    bm_h, off = orc.viewshed(z, obs)
+    bm = torch.from_numpy(bm_h.view(np.int64)).cuda()
+    sel, gains, nsel, _ = S.siting_greedy(bm, torch.from_numpy(off).cuda(),
+                                          S.observers_to_device(obs), 100, 100, 10, 10**9,
+                                          intervisible=True)
+    assert int(nsel.item()) == 3 and sel[:3].cpu().tolist() == [0, 1, 2]
+
+
 def test_greedy_ties_on_flat_terrain(S, orc):
     # flat terrain: equal disks everywhere.  Observers on a lattice of spacing
     # 2R+1 never overlap, so every round is a tie among all unselected ones
