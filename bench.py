@@ -14,9 +14,11 @@ Printed: ONE JSON line.  `value` is the viewshed throughput in cell-tests/s
 `siting_wall_s` is the whole step's wall time (the second half of the
 metric).  `roofline` describes the dominant kernel of the step (VIX);
 `cpu_baseline` times the oracle on the host cores on a bounded sample;
-`parity` compares the last timed step with the oracle (every viewshed and the
-oracle's SITE on its own bitmaps, VIX rows, every FINDMAX block), and the
-script exits with status 1 if they differ.
+`site_intervisible` times SITE with intervisibility (every pick after the
+first seen by an earlier one) on the last step's windows; `parity` compares
+the last timed step with the oracle (every viewshed, the oracle's SITE on its
+own bitmaps with and without intervisibility, VIX rows, every FINDMAX block),
+and the script exits with status 1 if they differ.
 """
 from __future__ import annotations
 
@@ -72,7 +74,8 @@ def traffic_from_profiles(kernel: str, src_hash: str):
         return None
 
 
-def cpu_baseline_and_parity(z_host, res, cfg, seconds: float, full_seconds: float):
+def cpu_baseline_and_parity(z_host, res, cfg, seconds: float, full_seconds: float,
+                            inter=None):
     """The oracle on this host's cores, on the outputs of the last timed step
     (`res`, a pass run with keep=True), as both the CPU baseline and the
     parity check of the timed run:
@@ -80,7 +83,9 @@ def cpu_baseline_and_parity(z_host, res, cfg, seconds: float, full_seconds: floa
         window compared with the device's: all of them when they fit in
         `full_seconds`, else a prefix of about `seconds` of work;
       - once every window is computed, the oracle's greedy SITE on its own
-        bitmaps against the step's selection and gains;
+        bitmaps against the step's selection and gains (and, given `inter` =
+        (selected, gains) of the device's SITE with intervisibility on the
+        step's windows, the oracle's intervisible greedy against it);
       - VIX on whole rows (LOS tests/s) against the step's counts;
       - FINDMAX of every block, from the step's counts, against its candidates.
     Returns (cpu_baseline, parity)."""
@@ -121,6 +126,13 @@ def cpu_baseline_and_parity(z_host, res, cfg, seconds: float, full_seconds: floa
         site_ok = bool(len(sel) == len(res.selected) and (sel == res.selected).all() and
                        (gains == res.gains).all())
     parity["site"] = site_ok
+    if done == M and inter is not None:
+        isel, igain, _, _ = oracle.greedy(or_bm, off, obs, nr, nc, cfg.max_obs,
+                                          target_cells(cfg.target_frac, nr, nc), lazy=True,
+                                          intervisible=True)
+        parity["site_intervisible"] = bool(len(isel) == len(inter[0]) and
+                                           (isel == inter[0]).all() and
+                                           (igain == inter[1]).all())
     del dev_bm, or_bm
     # VIX: whole rows until ~40% of the budget, compared with the step's counts
     rows = 1
@@ -150,7 +162,8 @@ def cpu_baseline_and_parity(z_host, res, cfg, seconds: float, full_seconds: floa
     fm_ok = len(want_c) == len(res.candidates) and bool((want_c == res.candidates).all())
     parity["findmax_blocks"] = (f"{nblk}/{nblk}" if fm_ok else
                                 f"mismatch ({len(want_c)} vs {len(res.candidates)} candidates)")
-    parity["ok"] = bool(bad_windows == 0 and site_ok is not False and bad_rows == 0 and fm_ok)
+    parity["ok"] = bool(bad_windows == 0 and site_ok is not False and bad_rows == 0 and fm_ok
+                        and parity.get("site_intervisible", True))
     cpu = {
         "value": vs_rate, "unit": "cell-tests/s", "cores": oracle.num_threads(), "kind": "oracle",
         "sample": f"oracle viewsheds of {done} of the {M} candidates ({cells} cell-tests, "
@@ -323,6 +336,32 @@ def main():
         "hbm_frac": (cells * 2 + bm_bytes) / vs_s / 1e9 / PEAK_HBM_GBS,
     }
 
+    # SITE with intervisibility (every pick after the first seen by an earlier
+    # one) on the last step's windows, timed on its own
+    obs_d = S.observers_to_device(last.observers)
+    off_d = torch.from_numpy(last.offsets).to(dev)
+    tgt = P.target_cells(cfg.target_frac, nr, nc)
+    ws_g = torch.empty(S.siting_greedy_workspace_size(len(last.observers)), dtype=torch.uint8,
+                       device=dev)
+    inter_ms = []
+    for i in range(1 + args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        isel, igain, inum, _ = S.siting_greedy(last.bitmaps, off_d, obs_d, nr, nc, cfg.max_obs, tgt,
+                                               ws=ws_g, intervisible=True)
+        e1.record()
+        e1.synchronize()
+        if i > 0:
+            inter_ms.append(e0.elapsed_time(e1))
+    im = int(inum.item())
+    inter_res = (isel[:im].cpu().numpy(), igain[:im].cpu().numpy())
+    inter = {"site_ms": float(np.median(inter_ms)), "selected": im,
+             "coverage_frac": int(inter_res[1].sum()) / (nr * nc),
+             "plain_site_ms": stage_ms["site"],
+             "plain_coverage_frac": last.coverage_cells / (nr * nc)}
+    log(f"[bench] SITE with intervisibility: {inter}")
+    del obs_d, off_d, ws_g
+
     # surrogate-ranked leg: the same path with the CNN score of the cells of
     # a stride grid as the FINDMAX key (weights trained on 4096^2 terrains)
     sur = None
@@ -355,7 +394,7 @@ def main():
         log("[bench] timing the oracle on the host and checking the last step against it")
         z_host = z.cpu().numpy()
         cpu, parity = cpu_baseline_and_parity(z_host, last, cfg, args.cpu_seconds,
-                                              args.parity_seconds)
+                                              args.parity_seconds, inter=inter_res)
         del z_host
         log(f"[bench] parity {parity}")
         log("[bench] timing the oracle on one host thread (per-core figure)")
@@ -387,6 +426,7 @@ def main():
         "roofline": roofline,
         "viewshed_roofline": vs_roof,
         "surrogate": sur,
+        "site_intervisible": inter,
         "cpu_baseline": cpu,
         "parity": parity,
     }

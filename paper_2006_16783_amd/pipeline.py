@@ -34,6 +34,7 @@ class SitingConfig:
     max_obs: int           # SITE observer cap
     target_frac: float     # SITE coverage target (fraction of all posts)
     vix_seed: int = 12345
+    intervisible: bool = False  # SITE: every pick after the first seen by an earlier one
 
     def to_dict(self):
         return asdict(self)
@@ -222,7 +223,8 @@ def run(z, cfg: SitingConfig, key=None, key_stride=1, sched=None, timing=True,
     bm = L.siting_viewshed_batch(z, obs_d, off_d, cfg.roi, sched=sched)
     T.mark("site")
     sel, gains, nsel, cum = L.siting_greedy(bm, off_d, obs_d, nrows, ncols, cfg.max_obs,
-                                            target_cells(cfg.target_frac, nrows, ncols))
+                                            target_cells(cfg.target_frac, nrows, ncols),
+                                            intervisible=cfg.intervisible)
     T.mark("d2h")
     m = int(nsel.item())
     sel_h = sel[:m].cpu().numpy()

@@ -9,8 +9,9 @@ its own bitmaps -- so a wrong bit anywhere fails.  That is the case for the
 4096^2 ROI-200 batch and the 16384^2 uneven batch.  The paper-scale ROI runs
 (32000^2, R 500 and 1000) are checked on sampled rows, blocks and windows
 plus a replay of the whole selection; a reduced R = 1000 terrain gets the full
-oracle chain from FINDMAX on.  A terrain of 4.6e9 posts checks the VIX
-streams of post indices (and a seed) above 2^32."""
+oracle chain from FINDMAX on.  SITE with intervisibility is checked on the same
+windows wherever the plain one is checked against the oracle.  A terrain of
+4.6e9 posts checks the VIX streams of post indices (and a seed) above 2^32."""
 import sys
 import time
 
@@ -63,6 +64,20 @@ def _oracle_chain(orc, S, z_host, cfg, res, cnt_or=None, t0=None):
     assert (sel == res.selected).all() and (gains == res.gains).all()
     assert (_u64(res.cumulative).reshape(cum.shape) == cum).all()
     _say("site:", len(sel), "selections, gains and cumulative equal", round(time.time() - t0, 1))
+    # the same windows sited with intervisibility (every pick after the first
+    # seen by an earlier one), on the device and by the oracle
+    tgt = P.target_cells(cfg.target_frac, nr, nc)
+    isel, igain, inum, icum = S.siting_greedy(res.bitmaps, torch.from_numpy(off).cuda(),
+                                              S.observers_to_device(obs), nr, nc, cfg.max_obs,
+                                              tgt, intervisible=True)
+    m = int(inum.item())
+    wsel, wgain, wcum, _ = orc.greedy(bm, off, obs, nr, nc, cfg.max_obs, tgt, lazy=True,
+                                      intervisible=True)
+    assert m == len(wsel)
+    assert (isel[:m].cpu().numpy() == wsel).all() and (igain[:m].cpu().numpy() == wgain).all()
+    assert (_u64(icum).reshape(wcum.shape) == wcum).all()
+    _say("site with intervisibility:", m, "selections equal, coverage",
+         round(int(wgain.sum()) / (nr * nc), 5), round(time.time() - t0, 1))
 
 
 def _pass_with_full_oracle(S, orc, cfg):
@@ -130,6 +145,16 @@ def test_uneven_16384_autotuned(S, orc):
     assert (sel[:m].cpu().numpy() == wsel).all() and (gains[:m].cpu().numpy() == wgain).all()
     assert (_u64(cum).reshape(wcum.shape) == wcum).all()
     _say("uneven site ok", m, round(time.time() - t0, 1))
+    # with intervisibility (windows of uneven size, heights 5-100 m)
+    sel, gains, nsel, cum = S.siting_greedy(bm, off_d, obs_d, n, n, 4000, n * n,
+                                            intervisible=True)
+    m = int(nsel.item())
+    wsel, wgain, wcum, _ = orc.greedy(want, off, obs, n, n, 4000, n * n, lazy=True,
+                                      intervisible=True)
+    assert m == len(wsel)
+    assert (sel[:m].cpu().numpy() == wsel).all() and (gains[:m].cpu().numpy() == wgain).all()
+    assert (_u64(cum).reshape(wcum.shape) == wcum).all()
+    _say("uneven site with intervisibility ok", m, round(time.time() - t0, 1))
 
 
 def _check_rows(orc, z_host, cnt_h_rows, cfg, rows):
