@@ -215,6 +215,36 @@ def cpu_per_core(seconds: float):
     return out
 
 
+def intervisible_leg(S, P, last, cfg, nr, nc, reps, dev, plain_site_ms):
+    """SITE with intervisibility on the windows of the pass `last` (run with
+    keep=True): median of `reps` timed runs after one warm-up; returns the
+    summary and (selected, gains) for the oracle check."""
+    import numpy as np
+    import torch
+    obs_d = S.observers_to_device(last.observers)
+    off_d = torch.from_numpy(last.offsets).to(dev)
+    tgt = P.target_cells(cfg.target_frac, nr, nc)
+    ws_g = torch.empty(S.siting_greedy_workspace_size(len(last.observers)), dtype=torch.uint8,
+                       device=dev)
+    inter_ms = []
+    for i in range(1 + reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        isel, igain, inum, _ = S.siting_greedy(last.bitmaps, off_d, obs_d, nr, nc, cfg.max_obs,
+                                               tgt, ws=ws_g, intervisible=True)
+        e1.record()
+        e1.synchronize()
+        if i > 0:
+            inter_ms.append(e0.elapsed_time(e1))
+    im = int(inum.item())
+    res = (isel[:im].cpu().numpy(), igain[:im].cpu().numpy())
+    out = {"site_ms": float(np.median(inter_ms)), "selected": im,
+           "coverage_frac": int(res[1].sum()) / (nr * nc), "plain_site_ms": plain_site_ms,
+           "plain_coverage_frac": last.coverage_cells / (nr * nc)}
+    log(f"[bench] SITE with intervisibility: {out}")
+    return out, res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -233,6 +263,8 @@ def main():
                     help="with --autotune: JSON file of tuned schedules to reuse and extend")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy (counter calibration for rocprof)")
+    ap.add_argument("--no-intervisible", action="store_true",
+                    help="skip the SITE-with-intervisibility leg")
     ap.add_argument("--surrogate-stride", type=int, default=8,
                     help="cell size of the CNN-ranked leg (0 skips that leg)")
     args = ap.parse_args()
@@ -281,8 +313,10 @@ def main():
             log(f"[bench] autotuned schedule {sched}: {['%.2f' % t for t in times]} ms")
         del bm
 
+    # paper-scale passes run for minutes: report each finished stage
+    prog = (lambda t: log(f"[bench]   {t}")) if cfg.roi >= 500 else None
     for i in range(args.warmup):
-        r = P.run(z, cfg, sched=sched)
+        r = P.run(z, cfg, sched=sched, progress=prog)
         log(f"[bench] warmup {i}: {r.stage_ms}")
     torch.cuda.synchronize()
     stage_tot = {}
@@ -291,7 +325,7 @@ def main():
     for i in range(args.steps):
         # the last step keeps its device outputs for the parity check (the
         # same work is enqueued either way)
-        r = P.run(z, cfg, sched=sched, keep=(i == args.steps - 1))
+        r = P.run(z, cfg, sched=sched, keep=(i == args.steps - 1), progress=prog)
         results.append(r)
         for k, v in r.stage_ms.items():
             stage_tot[k] = stage_tot.get(k, 0.0) + v
@@ -338,29 +372,10 @@ def main():
 
     # SITE with intervisibility (every pick after the first seen by an earlier
     # one) on the last step's windows, timed on its own
-    obs_d = S.observers_to_device(last.observers)
-    off_d = torch.from_numpy(last.offsets).to(dev)
-    tgt = P.target_cells(cfg.target_frac, nr, nc)
-    ws_g = torch.empty(S.siting_greedy_workspace_size(len(last.observers)), dtype=torch.uint8,
-                       device=dev)
-    inter_ms = []
-    for i in range(1 + args.steps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        isel, igain, inum, _ = S.siting_greedy(last.bitmaps, off_d, obs_d, nr, nc, cfg.max_obs, tgt,
-                                               ws=ws_g, intervisible=True)
-        e1.record()
-        e1.synchronize()
-        if i > 0:
-            inter_ms.append(e0.elapsed_time(e1))
-    im = int(inum.item())
-    inter_res = (isel[:im].cpu().numpy(), igain[:im].cpu().numpy())
-    inter = {"site_ms": float(np.median(inter_ms)), "selected": im,
-             "coverage_frac": int(inter_res[1].sum()) / (nr * nc),
-             "plain_site_ms": stage_ms["site"],
-             "plain_coverage_frac": last.coverage_cells / (nr * nc)}
-    log(f"[bench] SITE with intervisibility: {inter}")
-    del obs_d, off_d, ws_g
+    inter, inter_res = None, None
+    if not args.no_intervisible:
+        inter, inter_res = intervisible_leg(S, P, last, cfg, nr, nc, args.steps, dev,
+                                            stage_ms["site"])
 
     # surrogate-ranked leg: the same path with the CNN score of the cells of
     # a stride grid as the FINDMAX key (weights trained on 4096^2 terrains)

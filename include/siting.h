@@ -194,14 +194,17 @@ int siting_viewshed_default_schedule(int32_t rmax, siting_schedule *sched_host);
  *   sink SITING_SINK_COUNT : visible[i] = number of visible cells (including
  *        the observer), cells[i] = number of ROI-disk cells inside the
  *        terrain (the visibility index is visible/cells, Definitions);
- *        bitmaps may be NULL and offsets may be NULL.
+ *        bitmaps and offsets may be NULL when rmax <= 1087.
  *   rmax    : an upper bound of every observer's roi (sizes LDS).  The
  *        observer records are not read by the host: a record with roi > rmax
  *        or any field out of range is skipped (its bitmap words are left
  *        untouched; sink COUNT writes 0 and 0).  A whole-window bitmap fits
  *        LDS up to rmax 543; above that every observer is swept one
  *        quadrant at a time from global memory (the schedule's stage_rmax is
- *        then ignored), up to rmax 1087 (SITING_E_UNSUPPORTED beyond).
+ *        then ignored), up to rmax 1087; above that each observer's window is
+ *        cleared in `bitmaps` and marked there with atomic ORs (same bits),
+ *        so `bitmaps` and `offsets` are required with either sink (sink
+ *        COUNT uses them as scratch and leaves the windows there).
  *   ws, ws_bytes : workspace of siting_viewshed_workspace_size() bytes. */
 int siting_viewshed_batch(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
                           const siting_observer *obs, int64_t n, const int64_t *offsets,

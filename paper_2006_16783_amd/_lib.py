@@ -250,7 +250,7 @@ def siting_viewshed_batch(z, obs_dev, offsets_dev, rmax, order_dev=None, sched=N
         _ptr(z), nr, nc, ld, _ptr(obs_dev), n,
         _ptr(offsets_dev) if offsets_dev is not None else None,
         _ptr(order_dev) if order_dev is not None else None, int(rmax), sp, int(sink),
-        _ptr(bitmaps) if sink == SITING_SINK_BITMAP else None,
+        _ptr(bitmaps) if bitmaps is not None else None,
         _ptr(visible) if sink == SITING_SINK_COUNT else None,
         _ptr(cells) if sink == SITING_SINK_COUNT else None,
         _ptr(ws), ws.numel(), _stream(stream)))

@@ -17,6 +17,7 @@ int viewshed_launch(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
 int viewshed_lds_bytes(int32_t rmax, int32_t stage_rmax);
 int viewshed_max_dynamic_lds();
 bool quad_mode(int rmax);
+int viewshed_mode(int rmax);
 int validate_schedule(const siting_schedule &sc, const char *fn);
 }  // namespace siting
 
@@ -33,7 +34,16 @@ extern "C" int siting_autotune_candidates(int32_t rmax, siting_schedule *out_hos
     // (uneven batches: small observers from LDS, large ones through L2)
     // (windows too large for an LDS bitmap: quadrant mode, no staging)
     const bool quad = quad_mode(rmax);
-    std::vector<int> stages{quad ? 0 : rmax};
+    if (viewshed_mode(rmax) == 2) {
+        // global-bitmap mode uses no LDS: wavefronts per workgroup and
+        // workgroups per CU only
+        for (int waves : {8, 16})
+            for (int g : {1, 2, 4})
+                c.push_back(siting_schedule{waves, g, 0, 0});
+    }
+    std::vector<int> stages;
+    if (viewshed_mode(rmax) != 2)
+        stages.push_back(quad ? 0 : rmax);
     if (!quad) {
         stages.push_back(0);
         for (int st : {64, 100, 128, 160, 200, 256})

@@ -20,6 +20,10 @@
 //    memory, the quadrant's bitmap in LDS; its words go out at once, ORed
 //    where an earlier quadrant wrote the same word (the observer's row and
 //    the word holding its column).
+//  * Global-bitmap mode: when a quadrant's bitmap exceeds LDS too (ROI above
+//    1087), the workgroup clears the observer's output window in HBM and its
+//    rays mark cells there with atomic ORs (served by L2), the terrain read
+//    through the cache hierarchy; same rays and comparisons.
 //  * One ray per lane; consecutive lanes take consecutive boundary cells, so
 //    a wavefront's rays have similar lengths and similar LDS rows.
 //  * Exact integer slopes.  The per-quadrant elevation range bounds every
@@ -381,8 +385,10 @@ __global__ void viewshed_kernel(const int16_t *__restrict__ z, int64_t nrows, in
                                 const int32_t *__restrict__ order, int sink,
                                 uint64_t *__restrict__ bitmaps, uint32_t *__restrict__ visible,
                                 uint32_t *__restrict__ cells, uint32_t *queue, int rmax,
-                                int stage_rmax, int dma, int quad)
+                                int stage_rmax, int dma, int mode)
 {
+    // mode 0: window bitmap in LDS; 1: quadrant mode; 2: global-bitmap mode
+    const int quad = mode == 1;
     extern __shared__ uint32_t lds[];
     __shared__ int64_t s_task;
     __shared__ int s_red[2 * 16];
@@ -430,6 +436,71 @@ __global__ void viewshed_kernel(const int16_t *__restrict__ z, int64_t nrows, in
         const int R2 = R * R;
         const int16_t *zo = z + y * ld + x;
         const int E = (int)zo[0] + o.h_t;
+
+        if (mode == 2) {
+            // the window bitmap in HBM (with the count sink, the caller's
+            // bitmaps serve as scratch): cleared, then marked by every ray of
+            // the four quadrants with atomic ORs on its dwords (bit b of the
+            // row-major bit array is bit b & 31 of dword b >> 5)
+            uint64_t *out = bitmaps + offsets[i];
+            const int words = rows * nw;
+            for (int e = tid; e < words; e += nthreads)
+                out[e] = 0;
+            __threadfence();
+            __syncthreads();
+            uint32_t *gbm = reinterpret_cast<uint32_t *>(out);
+            const int GP = nw * 64;  // bits per window row (< 2^31 / rows)
+            const int P0g = (int)(y - ylo) * GP + (int)(x - (w0 << 6));
+            if (tid == 0)
+                atomicOr(&gbm[P0g >> 5], 1u << (P0g & 31));
+            const int n0 = ex_p >= 1 ? ex_p + ey_p : 0;
+            const int n1 = n0 + (ey_p >= 1 ? ey_p + ex_m : 0);
+            const int n2 = n1 + (ex_m >= 1 ? ex_m + ey_m : 0);
+            const int n3 = n2 + (ey_m >= 1 ? ey_m + ex_p : 0);
+            GlobalSrc src{zo};
+            for (int rho = tid; rho < n3; rho += nthreads) {
+                const int qd = rho < n0 ? 0 : rho < n1 ? 1 : rho < n2 ? 2 : 3;
+                const int base = qd == 0 ? 0 : qd == 1 ? n0 : qd == 2 ? n1 : n2;
+                const Quadrant Q = make_quadrant(qd, ex_p, ex_m, ey_p, ey_m, GP, (int)ld);
+                int du, dv;
+                ray_target(Q, rho - base, du, dv);
+                sweep<false, true>(src, Q.gu, Q.gv, gbm, P0g, Q.bu, Q.bv, du, dv, R2, E, o.h_r);
+            }
+            __threadfence();
+            __syncthreads();
+            if (sink == SITING_SINK_COUNT) {
+                // visible cells: the window's set bits; disk cells row by row
+                uint32_t vis = 0, cnt = 0;
+                for (int e = tid; e < words; e += nthreads)
+                    vis += (uint32_t)__popcll(out[e]);
+                for (int row = tid; row < rows; row += nthreads) {
+                    const int dy = (int)(ylo + row - y);
+                    const int hw = isqrt_floor(R2 - dy * dy);
+                    const int64_t a = x - hw < xlo ? xlo : x - hw;
+                    const int64_t b = x + hw > xhi ? xhi : x + hw;
+                    if (b >= a)
+                        cnt += (uint32_t)(b - a + 1);
+                }
+                vis = wave_sum_u32(vis);
+                cnt = wave_sum_u32(cnt);
+                if (lane == 0) {
+                    s_sum[wave] = vis;
+                    s_sum[16 + wave] = cnt;
+                }
+                __syncthreads();
+                if (tid == 0) {
+                    uint32_t tv = 0, tc = 0;
+                    for (int w = 0; w < nwaves; w++) {
+                        tv += s_sum[w];
+                        tc += s_sum[16 + w];
+                    }
+                    visible[i] = tv;
+                    cells[i] = tc;
+                }
+                __syncthreads();
+            }
+            continue;
+        }
 
         if (quad) {
             // one quadrant at a time in LDS, terrain from global memory; each
@@ -755,12 +826,22 @@ int viewshed_max_dynamic_lds()
 }
 
 // Windows whose bitmap exceeds LDS run in quadrant mode (terrain from global
-// memory, staging off).
-bool quad_mode(int rmax) { return bm_bytes(rmax) > viewshed_max_dynamic_lds(); }
+// memory, staging off); windows whose quadrant bitmap exceeds it too, in
+// global-bitmap mode.
+int viewshed_mode(int rmax)
+{
+    if (bm_bytes(rmax) <= viewshed_max_dynamic_lds())
+        return 0;
+    return bmq_bytes(rmax) <= viewshed_max_dynamic_lds() ? 1 : 2;
+}
+bool quad_mode(int rmax) { return viewshed_mode(rmax) != 0; }
 
 int lds_bytes_for(int rmax, int stage_rmax)
 {
-    if (quad_mode(rmax))
+    const int mode = viewshed_mode(rmax);
+    if (mode == 2)
+        return 0;
+    if (mode == 1)
         return bmq_bytes(rmax);
     return bm_bytes(rmax) + zq_bytes(std::min(stage_rmax, rmax));
 }
@@ -772,8 +853,13 @@ int viewshed_launch(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
                     uint64_t *bitmaps, uint32_t *visible, uint32_t *cells, void *ws,
                     hipStream_t s)
 {
-    const int quad = quad_mode(rmax) ? 1 : 0;
-    int stage = quad ? 0 : std::min(sc.stage_rmax, rmax);
+    const int mode = viewshed_mode(rmax);
+    if (mode == 2 && (bitmaps == nullptr || offsets == nullptr)) {
+        set_error("siting_viewshed_batch: above rmax 1087 the windows are built in `bitmaps` "
+                  "(with offsets), also for the count sink");
+        return SITING_E_INVALID;
+    }
+    int stage = mode ? 0 : std::min(sc.stage_rmax, rmax);
     int lds = lds_bytes_for(rmax, stage);
     if (lds > viewshed_max_dynamic_lds()) {
         set_error("siting_viewshed_batch: schedule needs %d bytes of LDS (at most %d)", lds,
@@ -794,7 +880,7 @@ int viewshed_launch(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
     const int dma = ld % 2 == 0 && ncols % 2 == 0 && reinterpret_cast<uintptr_t>(z) % 4 == 0;
     hipLaunchKernelGGL(viewshed_kernel, dim3((unsigned)grid), dim3(64 * sc.waves), (size_t)lds, s,
                        z, nrows, ncols, ld, obs, n, offsets, order, sink, bitmaps, visible, cells,
-                       queue, rmax, stage, dma, quad);
+                       queue, rmax, stage, dma, mode);
     return check_launch("viewshed_kernel");
 }
 
@@ -809,6 +895,12 @@ int viewshed_default_schedule(int32_t rmax, siting_schedule *sc)
         sc->waves = std::max(2, std::min(8, (4 * rmax + 63) / 64 + 1));
         sc->stage_rmax = rmax;
         sc->groups_per_cu = std::max(1, std::min(8, budget / lds_staged));
+    } else if (viewshed_mode(rmax) == 2) {
+        // no LDS bitmap: two workgroups of 16 wavefronts per CU (8R rays
+        // per observer)
+        sc->stage_rmax = 0;
+        sc->waves = 16;
+        sc->groups_per_cu = 2;
     } else if (quad_mode(rmax)) {
         // one workgroup per CU holds a quadrant's bitmap; its 2R rays fill
         // 16 wavefronts about twice

@@ -61,6 +61,8 @@ CONFIGS = {
                                      96, 20, 5000, 1.0),
     "west_46400_r1000": SitingConfig("west_46400_r1000", 46400, 2.4, 2706, 1, 1000, 100, 10, 10,
                                      139, 20, 5647, 1.0),
+    "west_46400_r2000": SitingConfig("west_46400_r2000", 46400, 2.4, 2706, 1, 2000, 100, 10, 10,
+                                     70, 20, 3347, 1.0),
 }
 
 
@@ -190,17 +192,28 @@ class _Timer:
 
 
 def run(z, cfg: SitingConfig, key=None, key_stride=1, sched=None, timing=True,
-        surrogate=None, keep=False) -> SitingResult:
+        surrogate=None, keep=False, progress=None) -> SitingResult:
     """One pass of the whole siting path over the device terrain z (int16,
     resident in HBM).  The FINDMAX ranking is the VIX count, or `key` (a
     float32 device tensor) when given, or the CNN score of the cells of a
     stride grid when surrogate=(params, stride) is given (computed inside the
     timed pass).  keep=True also returns the pass's device tensors (no extra
-    work is enqueued)."""
+    work is enqueued).  progress(text): called when each stage has finished
+    (the host waits for it), for passes that run for minutes."""
     import torch
     nrows, ncols = z.shape
     dev = z.device
     T = _Timer(timing)
+    if progress is not None:
+        t_start = time.perf_counter()
+        mark0 = T.mark
+
+        def mark(name):
+            torch.cuda.synchronize()
+            if T.events:
+                progress(f"{T.events[-1][0]} done at {time.perf_counter() - t_start:.1f} s")
+            mark0(name)
+        T.mark = mark
     T.mark("vix" if key is None and surrogate is None else "score")
     if surrogate is not None:
         params, key_stride = surrogate

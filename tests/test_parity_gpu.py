@@ -204,6 +204,44 @@ def test_viewshed_quadrant_mode(S, orc, seed, roi, shape):
     assert (cells.cpu().numpy().astype(np.uint32) == wc).all()
 
 
+@pytest.mark.timeout(600)
+def test_viewshed_global_bitmap_mode(S, orc):
+    # ROI 1100-2000 (the paper's second US-West run uses 2000): a quadrant's
+    # bitmap exceeds LDS, so each window is cleared and marked in HBM.  A
+    # 4600^2 terrain (so R = 2000 windows are clipped on one side or more),
+    # the corners and edge midpoints included, every window against the
+    # oracle; then SITE on those windows against the oracle's greedy
+    seed, nr, nc, roi = 71, 4600, 4600, (1100, 2000)
+    _say("viewshed global-bitmap mode", seed, nr, nc, roi)
+    z = _terrain(nr, 2.4, 2700, seed, ncols=nc)
+    obs = _quadrant_observers(nr, nc, 24, seed, roi, (5, 100))
+    got, want = _viewshed_case(S, orc, z, obs, roi[1])
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, ("viewshed words differ", bad[:8])
+    _say("windows equal", len(obs))
+    # the count sink builds the windows in the caller's bitmaps (required here)
+    off = S.siting_viewshed_layout(obs, nr, nc)
+    zd, obs_d, off_d = torch.from_numpy(z).cuda(), S.observers_to_device(obs), torch.from_numpy(off).cuda()
+    with pytest.raises(S.SitingError) as ei:
+        S.siting_viewshed_batch(zd, obs_d, None, roi[1], sink=S.SITING_SINK_COUNT)
+    assert ei.value.code == -1
+    scratch = torch.empty(int(off[-1]), dtype=torch.int64, device="cuda")
+    vis, cells = S.siting_viewshed_batch(zd, obs_d, off_d, roi[1], sink=S.SITING_SINK_COUNT,
+                                         bitmaps=scratch)
+    wv, wc = orc.viewshed_count(z, obs)
+    assert (vis.cpu().numpy().astype(np.uint32) == wv).all()
+    assert (cells.cpu().numpy().astype(np.uint32) == wc).all()
+    assert (_u64(scratch) == want).all()
+    wsel, wgain, wcum, _ = orc.greedy(want, off, obs, nr, nc, 20, nr * nc, lazy=True)
+    bm = torch.from_numpy(want.view(np.int64)).cuda()
+    sel, gains, nsel, cum = S.siting_greedy(bm, torch.from_numpy(off).cuda(),
+                                            S.observers_to_device(obs), nr, nc, 20, nr * nc)
+    m = int(nsel.item())
+    assert m == len(wsel) and (sel[:m].cpu().numpy() == wsel).all()
+    assert (gains[:m].cpu().numpy() == wgain).all()
+    assert (_u64(cum).reshape(-1) == wcum.reshape(-1)).all()
+
+
 @pytest.mark.parametrize("seed,roi,height,shape", [
     (41, (1, 40), (0, 30), (200, 230)),
     (42, (30, 90), (5, 100), (300, 280)),

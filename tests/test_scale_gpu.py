@@ -7,7 +7,8 @@ on its own counts, its viewsheds of its own candidates, and its greedy SITE on
 its own bitmaps -- so a wrong bit anywhere fails.  That is the case for the
 46400^2 workload (2.15e9 posts, 81,920 candidates, 4096 observers), the
 4096^2 ROI-200 batch and the 16384^2 uneven batch.  The paper-scale ROI runs
-(32000^2, R 500 and 1000) are checked on sampled rows, blocks and windows
+(32000^2 at R 500 and 1000, 46400^2 at R 1000 and 2000) are checked on sampled
+rows, blocks and windows
 plus a replay of the whole selection; a reduced R = 1000 terrain gets the full
 oracle chain from FINDMAX on.  SITE with intervisibility is checked on the same
 windows wherever the plain one is checked against the oracle.  A terrain of
@@ -208,8 +209,10 @@ def _paper_roi_pass(S, orc, name, n_views):
     # SITE: the first pick is the largest viewshed (ties to the lowest index;
     # visible counts from the count sink), and replaying the selection over
     # the device bitmaps gives every recorded gain
-    vis, _ = S.siting_viewshed_batch(z, S.observers_to_device(obs), None, cfg.roi,
-                                     sink=S.SITING_SINK_COUNT)
+    # (above ROI 1087 the count sink rebuilds each window in the bitmaps it
+    # is given: the pass's own, rewritten with the same bits)
+    vis, _ = S.siting_viewshed_batch(z, S.observers_to_device(obs), torch.from_numpy(off).cuda(),
+                                     cfg.roi, sink=S.SITING_SINK_COUNT, bitmaps=res.bitmaps)
     vis = vis.cpu().numpy().astype(np.int64)
     assert res.selected[0] == int(np.argmax(vis)) and res.gains[0] == vis.max()
     W = (cfg.n + 63) // 64
@@ -242,6 +245,20 @@ def test_paper_roi_east_32000_r500(S, orc):
     # the paper's first billion-post run: 32000^2, ROI 500, h 100/10,
     # 193x193 blocks x 20 = 744,980 candidates, SITE to 6543
     _paper_roi_pass(S, orc, "east_32000_r500", 48)
+
+
+@pytest.mark.timeout(900)
+def test_paper_roi_west_46400_r1000(S, orc):
+    # the paper's first US-West run: 46400^2 (0-2706 m), ROI 1000, h 100/10,
+    # 139x139 blocks x 20 = 386,420 candidates, SITE to 5647
+    _paper_roi_pass(S, orc, "west_46400_r1000", 24)
+
+
+@pytest.mark.timeout(900)
+def test_paper_roi_west_46400_r2000(S, orc):
+    # the paper's second US-West run: ROI 2000 (global-bitmap viewsheds),
+    # 70x70 blocks x 20 = 98,000 candidates, SITE to 3347
+    _paper_roi_pass(S, orc, "west_46400_r2000", 16)
 
 
 @pytest.mark.timeout(600)
