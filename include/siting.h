@@ -297,6 +297,23 @@ int siting_greedy_intervisible(const uint64_t *bitmaps, const int64_t *offsets,
                                uint64_t *cumulative, int64_t *selected, int64_t *gains,
                                int32_t *nselected, void *ws, size_t ws_bytes, void *stream);
 
+/* The same selection as siting_greedy for large windows, each round spread
+ * over the GPU: up to `batch` stale top candidates (the top candidate of the
+ * top block and of the blocks whose maxima carry the largest gain bounds) are
+ * re-evaluated by one workgroup each, then the largest key overall is taken
+ * if it is fresh (the stage's bound makes that the plain greedy choice).
+ * Rounds are enqueued by the host in batches and the call SYNCHRONIZES
+ * `stream` (it returns when the selection is complete).  Arguments, outputs
+ * and errors as siting_greedy; 1 <= batch <= 1024; ws, ws_bytes:
+ * siting_greedy_workspace_size(n) bytes.  Meant for windows of thousands of
+ * words (ROI in the hundreds and more), where one workgroup per round is
+ * bound by its own memory latency. */
+int siting_greedy_parallel(const uint64_t *bitmaps, const int64_t *offsets,
+                           const siting_observer *obs, int64_t n, int64_t nrows, int64_t ncols,
+                           int32_t max_obs, int64_t target_cells, int32_t batch,
+                           uint64_t *cumulative, int64_t *selected, int64_t *gains,
+                           int32_t *nselected, void *ws, size_t ws_bytes, void *stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * selection as siting_greedy, identical outputs, without a workspace

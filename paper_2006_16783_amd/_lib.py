@@ -73,6 +73,8 @@ def _load():
         "siting_greedy_workspace_size": ([i64], sz),
         "siting_greedy": ([P, P, P, i64, i64, i64, i32, i64, P, P, P, P, P, sz, P], C.c_int),
         "siting_greedy_noalloc": ([P, P, P, i64, i64, i64, i32, i64, P, P, P, P, P], C.c_int),
+        "siting_greedy_parallel": ([P, P, P, i64, i64, i64, i32, i64, i32, P, P, P, P, P, sz, P],
+                                   C.c_int),
         "siting_greedy_intervisible": ([P, P, P, i64, i64, i64, i32, i64, P, P, P, P, P, sz, P],
                                        C.c_int),
         "siting_cnn_param_count": ([], C.c_int),
@@ -315,10 +317,11 @@ def siting_greedy_workspace_size(n: int) -> int:
 
 
 def siting_greedy(bitmaps, offsets_dev, obs_dev, nrows, ncols, max_obs, target_cells,
-                  cumulative=None, ws=None, stream=None, intervisible=False):
+                  cumulative=None, ws=None, stream=None, intervisible=False, parallel=0):
     """Greedy SITE.  Returns (selected, gains, nselected, cumulative) device
     tensors; selected/gains hold max_obs entries, the first nselected valid.
-    intervisible=True calls siting_greedy_intervisible."""
+    intervisible=True calls siting_greedy_intervisible; parallel=m > 0 calls
+    siting_greedy_parallel with batch m (synchronizes the stream)."""
     import torch
     dev = bitmaps.device
     n = obs_dev.shape[0]
@@ -330,6 +333,14 @@ def siting_greedy(bitmaps, offsets_dev, obs_dev, nrows, ncols, max_obs, target_c
     nsel = torch.zeros(1, dtype=torch.int32, device=dev)
     if ws is None:
         ws = torch.empty(max(siting_greedy_workspace_size(n), 1), dtype=torch.uint8, device=dev)
+    if parallel and intervisible:
+        raise ValueError("the parallel-round SITE has no intervisibility variant")
+    if parallel:
+        _check("siting_greedy_parallel", _lib.siting_greedy_parallel(
+            _ptr(bitmaps), _ptr(offsets_dev), _ptr(obs_dev), n, int(nrows), int(ncols),
+            int(max_obs), int(target_cells), int(parallel), _ptr(cumulative), _ptr(selected),
+            _ptr(gains), _ptr(nsel), _ptr(ws), ws.numel(), _stream(stream)))
+        return selected, gains, nsel, cumulative
     name = "siting_greedy_intervisible" if intervisible else "siting_greedy"
     _check(name, getattr(_lib, name)(
         _ptr(bitmaps), _ptr(offsets_dev), _ptr(obs_dev), n, int(nrows), int(ncols), int(max_obs),

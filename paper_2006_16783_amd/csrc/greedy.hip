@@ -684,6 +684,297 @@ __global__ __launch_bounds__(64 * kWaves) void greedy_run(
         *nselected = t;
 }
 
+// ---------------------------------------------------------------------------
+// SITE for large windows, rounds spread over the GPU (host-driven).  The same
+// lazy greedy and the same selection: in every round a set S of candidates
+// (the top candidate of the top block, then of the blocks whose maxima carry
+// the m largest gain bounds) is re-evaluated by one workgroup each, in
+// parallel, and then the largest key overall is taken if it is fresh (a fresh
+// key at least every stale bound is the plain greedy choice).  A stale top
+// after the evaluation is in the next round's S, so every round either selects
+// or makes a stale top exact.  Device state: key, fresh, bmax, bfr as in the
+// one-workgroup kernel, plus the round control below.
+constexpr int kParMax = 1024;  // largest S
+
+struct ParCtl {
+    int32_t t;           // observers selected so far
+    int32_t done;        // the run has ended (every later kernel returns)
+    int32_t or_pending;  // this round selected sel_i, whose window still goes into C
+    int32_t nS;          // entries of S this round
+    int64_t covered;
+    int64_t sel_i;
+};
+
+__global__ void gpar_init(ParCtl *ctl, int32_t max_obs, int64_t target)
+{
+    ctl->t = 0;
+    ctl->done = (max_obs <= 0 || target <= 0) ? 1 : 0;
+    ctl->or_pending = 0;
+    ctl->nS = 0;
+    ctl->covered = 0;
+    ctl->sel_i = -1;
+}
+
+// S for this round: the top block first, then blocks whose maximum's gain
+// exceeds theta, then blocks at theta, at most m; theta is the m-th largest
+// gain among the non-empty block maxima (radix selection over its 4 bytes).
+__global__ __launch_bounds__(1024) void gpar_select(const uint64_t *__restrict__ bmax, int nb,
+                                                   ParCtl *ctl, int64_t *__restrict__ S_cand,
+                                                   int32_t *__restrict__ S_blk, int m)
+{
+    __shared__ uint32_t hist[256];
+    __shared__ uint32_t s_prefix, s_mask, s_rem, s_count, s_nz;
+    __shared__ uint64_t s_wmax[16];
+    __shared__ int s_topb;
+    if (ctl->done)
+        return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint64_t mk = 0;
+    uint32_t nz = 0;
+    for (int b = tid; b < nb; b += 1024) {
+        const uint64_t v = bmax[b];
+        mk = v > mk ? v : mk;
+        nz += v != 0;
+    }
+    mk = wave_max_u64(mk);
+    nz = wave_sum_u32(nz);
+    if (tid == 0) {
+        s_nz = 0;
+        s_prefix = 0;
+        s_mask = 0;
+        s_rem = (uint32_t)m;
+    }
+    __syncthreads();
+    if (lane == 0) {
+        s_wmax[wave] = mk;
+        atomicAdd(&s_nz, nz);
+    }
+    __syncthreads();
+    uint64_t top = 0;
+#pragma unroll
+    for (int w = 0; w < 16; w++)
+        top = s_wmax[w] > top ? s_wmax[w] : top;
+    const uint32_t nonzero = s_nz;
+    if (top == 0) {
+        if (tid == 0)
+            ctl->nS = 0;
+        return;
+    }
+    const int64_t top_i = (int64_t)(0xFFFFFFFFull - (top & 0xFFFFFFFFull));
+    uint32_t theta = 0;
+    if (nonzero > (uint32_t)m) {
+        for (int pass = 0; pass < 4; pass++) {
+            const int shift = 24 - 8 * pass;
+            if (tid < 256)
+                hist[tid] = 0;
+            __syncthreads();
+            const uint32_t pre = s_prefix, msk = s_mask;
+            for (int b = tid; b < nb; b += 1024) {
+                const uint64_t v = bmax[b];
+                const uint32_t g = (uint32_t)(v >> 32);
+                if (v != 0 && (g & msk) == pre)
+                    atomicAdd(&hist[(g >> shift) & 0xFFu], 1u);
+            }
+            __syncthreads();
+            if (tid == 0) {
+                uint32_t cum = 0, rem = s_rem;
+                int sel = 0;
+                for (int d = 255; d >= 0; d--) {
+                    if (cum + hist[d] >= rem) {
+                        sel = d;
+                        rem -= cum;
+                        break;
+                    }
+                    cum += hist[d];
+                }
+                s_rem = rem;
+                s_prefix = pre | ((uint32_t)sel << shift);
+                s_mask = msk | (0xFFu << shift);
+            }
+            __syncthreads();
+        }
+        theta = s_prefix;
+    }
+    if (tid == 0) {
+        s_topb = (int)(top_i / kGreedyBlock);
+        s_count = 1;
+        S_blk[0] = s_topb;
+        S_cand[0] = top_i;
+    }
+    __syncthreads();
+    const int topb = s_topb;
+    for (int phase = 0; phase < 2; phase++) {
+        for (int b = tid; b < nb; b += 1024) {
+            const uint64_t v = bmax[b];
+            const uint32_t g = (uint32_t)(v >> 32);
+            if (v == 0 || b == topb || (phase == 0 ? g <= theta : g != theta))
+                continue;
+            const uint32_t slot = atomicAdd(&s_count, 1u);
+            if (slot < (uint32_t)m) {
+                S_blk[slot] = b;
+                S_cand[slot] = (int64_t)(0xFFFFFFFFull - (v & 0xFFFFFFFFull));
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0)
+        ctl->nS = (int)(s_count < (uint32_t)m ? s_count : (uint32_t)m);
+}
+
+// One workgroup per entry of S: a stale candidate's gain |V \ C| afresh, then
+// its block's maximum (every block appears in S at most once).
+__global__ __launch_bounds__(256) void gpar_eval(
+    const uint64_t *__restrict__ bitmaps, const int64_t *__restrict__ offsets,
+    const siting_observer *__restrict__ obs, int64_t n, int64_t nrows, int64_t ncols,
+    const uint64_t *__restrict__ C, uint64_t *key, int32_t *fresh, const ParCtl *ctl,
+    const int64_t *__restrict__ S_cand, const int32_t *__restrict__ S_blk, uint64_t *bmax,
+    int32_t *bfr)
+{
+    __shared__ uint32_t s_part[4];
+    if (ctl->done || (int)blockIdx.x >= ctl->nS)
+        return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int32_t t = ctl->t;
+    const int64_t i = S_cand[blockIdx.x];
+    const int b = S_blk[blockIdx.x];
+    uint64_t ki = 0;
+    int32_t fi = 0;
+    bool over = false;
+    if (fresh[i] != t) {
+        const siting_observer o = obs[i];
+        uint32_t cnt = 0;
+        if (obs_ok(o, nrows, ncols)) {
+            const Win w = window_of(o, nrows, ncols);
+            const uint64_t *v = bitmaps + offsets[i];
+            const int64_t W = (ncols + 63) >> 6;
+            const int words = w.rows * w.nw;
+            // four words per thread in flight; row and column by division
+            for (int e0 = 0; e0 < words; e0 += 1024) {
+                uint64_t vv[4], cc[4];
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const int e = e0 + u * 256 + tid;
+                    vv[u] = 0;
+                    cc[u] = 0;
+                    if (e < words) {
+                        const int r = e / w.nw, c = e - r * w.nw;
+                        vv[u] = v[e];
+                        cc[u] = C[(w.ylo + r) * W + w.w0 + c];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; u++)
+                    cnt += (uint32_t)__popcll(vv[u] & ~cc[u]);
+            }
+        }
+        cnt = wave_sum_u32(cnt);
+        if (lane == 0)
+            s_part[wave] = cnt;
+        __syncthreads();
+        const uint64_t gain = (uint64_t)s_part[0] + s_part[1] + s_part[2] + s_part[3];
+        ki = (gain << 32) | (0xFFFFFFFFull - (uint64_t)i);
+        fi = t;
+        over = true;
+        if (tid == 0) {
+            key[i] = ki;
+            fresh[i] = fi;
+        }
+    }
+    if (wave == 0) {
+        uint64_t v;
+        int32_t f;
+        // the new key of i is taken from registers, not read back
+        wave_block_max(key, fresh, n, b, lane, over ? i : -1, ki, fi, v, f);
+        if (lane == 0) {
+            bmax[b] = v;
+            bfr[b] = f;
+        }
+    }
+}
+
+// The round's decision (one workgroup): the largest key overall; a fresh one
+// is selected (a zero gain or an exhausted key set ends the run).
+__global__ __launch_bounds__(1024) void gpar_decide(
+    uint64_t *key, int32_t *fresh, uint64_t *bmax, int32_t *bfr, int nb, int64_t n,
+    int32_t max_obs, int64_t target, ParCtl *ctl, int64_t *__restrict__ selected,
+    int64_t *__restrict__ gains)
+{
+    __shared__ uint64_t s_wmax[16];
+    if (ctl->done)
+        return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint64_t mk = 0;
+    for (int b = tid; b < nb; b += 1024) {
+        const uint64_t v = bmax[b];
+        mk = v > mk ? v : mk;
+    }
+    mk = wave_max_u64(mk);
+    if (lane == 0)
+        s_wmax[wave] = mk;
+    __syncthreads();
+    uint64_t top = 0;
+#pragma unroll
+    for (int w = 0; w < 16; w++)
+        top = s_wmax[w] > top ? s_wmax[w] : top;
+    const int32_t t = ctl->t;
+    const int64_t i = (int64_t)(0xFFFFFFFFull - (top & 0xFFFFFFFFull));
+    const uint64_t g = top >> 32;
+    const int bi = (int)(i / kGreedyBlock);
+    const bool stale = top != 0 && bfr[bi] != t;
+    const bool end = top == 0 || i >= n || (!stale && g == 0);
+    const bool take = !end && !stale;
+    if (wave == 0) {
+        if (take) {
+            // i's key drops to a zero gain, fresh from now on; its block's maximum
+            const uint64_t ki = 0xFFFFFFFFull - (uint64_t)i;
+            uint64_t v;
+            int32_t f;
+            wave_block_max(key, fresh, n, bi, lane, i, ki, t + 1, v, f);
+            if (lane == 0) {
+                key[i] = ki;
+                fresh[i] = t + 1;
+                bmax[bi] = v;
+                bfr[bi] = f;
+                selected[t] = i;
+                gains[t] = (int64_t)g;
+                const int64_t cov = ctl->covered + (int64_t)g;
+                ctl->covered = cov;
+                ctl->sel_i = i;
+                ctl->or_pending = 1;
+                ctl->t = t + 1;
+                ctl->done = (t + 1 >= max_obs || cov >= target) ? 1 : 0;
+            }
+        } else if (lane == 0) {
+            ctl->or_pending = 0;
+            if (end)
+                ctl->done = 1;
+        }
+    }
+}
+
+// C |= V of the observer selected this round, spread over the grid.
+__global__ __launch_bounds__(256) void gpar_or(const uint64_t *__restrict__ bitmaps,
+                                               const int64_t *__restrict__ offsets,
+                                               const siting_observer *__restrict__ obs,
+                                               int64_t nrows, int64_t ncols, uint64_t *C,
+                                               const ParCtl *ctl)
+{
+    if (!ctl->or_pending)
+        return;
+    const int64_t i = ctl->sel_i;
+    const siting_observer o = obs[i];
+    const Win w = window_of(o, nrows, ncols);
+    const uint64_t *v = bitmaps + offsets[i];
+    const int64_t W = (ncols + 63) >> 6;
+    const int words = w.rows * w.nw;
+    for (int e = blockIdx.x * 256 + threadIdx.x; e < words; e += gridDim.x * 256) {
+        const int r = e / w.nw, c = e - r * w.nw;
+        C[(w.ylo + r) * W + w.w0 + c] |= v[e];
+    }
+}
+
+__global__ void gpar_finish(const ParCtl *ctl, int32_t *nselected) { *nselected = ctl->t; }
+
 }  // namespace
 }  // namespace siting
 
@@ -706,6 +997,13 @@ static constexpr size_t greedy_inter_ws_bytes(int64_t n)
     return greedy_ws_bytes(n) + align256((size_t)n * 8) + align256((size_t)n * 4) +
            align256((size_t)n * 8);
 }
+// The parallel-round path: the round control and the set S after the
+// one-workgroup layout.
+static constexpr size_t greedy_par_ws_bytes(int64_t n)
+{
+    return greedy_ws_bytes(n) + align256(sizeof(ParCtl)) + align256((size_t)kParMax * 8) +
+           align256((size_t)kParMax * 4);
+}
 
 // The allocation-free entry point keeps its workspace in this array (one
 // copy per device, held until the process ends).  Host code must not pass
@@ -719,7 +1017,8 @@ extern "C" size_t siting_greedy_workspace_size(int64_t n)
 {
     if (n < 0)
         return 0;
-    return greedy_inter_ws_bytes(n);  // enough for both entry points
+    // enough for every entry point
+    return std::max(greedy_inter_ws_bytes(n), greedy_par_ws_bytes(n));
 }
 
 // Argument validation shared by both entry points (host only); SITING_OK or
@@ -869,6 +1168,101 @@ extern "C" int siting_greedy_intervisible(const uint64_t *bitmaps, const int64_t
         return rc;
     return greedy_launch(bitmaps, offsets, obs, n, nrows, ncols, max_obs, target_cells,
                          cumulative, selected, gains, nselected, ws, stream, true);
+}
+
+extern "C" int siting_greedy_parallel(const uint64_t *bitmaps, const int64_t *offsets,
+                                      const siting_observer *obs, int64_t n, int64_t nrows,
+                                      int64_t ncols, int32_t max_obs, int64_t target_cells,
+                                      int32_t batch, uint64_t *cumulative, int64_t *selected,
+                                      int64_t *gains, int32_t *nselected, void *ws,
+                                      size_t ws_bytes, void *stream)
+{
+    clear_error();
+    const char *fn = "siting_greedy_parallel";
+    int rc = greedy_check(fn, bitmaps, offsets, obs, n, nrows, ncols, max_obs, cumulative,
+                          selected, gains, nselected);
+    if (rc != SITING_OK)
+        return rc;
+    SITING_REQUIRE(batch >= 1 && batch <= kParMax, "%s: batch %d outside 1..%d", fn, batch,
+                   kParMax);
+    SITING_REQUIRE(n <= (int64_t)kGreedyMaxBlocks * kGreedyBlock,
+                   "%s: %lld candidates above the supported maximum", fn, (long long)n);
+    const size_t need = greedy_par_ws_bytes(n);
+    if (ws == nullptr || ws_bytes < need) {
+        set_error("%s: workspace of %zu bytes needed", fn, need);
+        return SITING_E_WORKSPACE;
+    }
+    const int nb = (int)((n + kGreedyBlock - 1) / kGreedyBlock);
+    char *wsb = reinterpret_cast<char *>(ws);
+    uint64_t *key = reinterpret_cast<uint64_t *>(wsb);
+    wsb += align256((size_t)n * 8);
+    int32_t *fresh = reinterpret_cast<int32_t *>(wsb);
+    wsb += align256((size_t)n * 4);
+    uint64_t *bmax = reinterpret_cast<uint64_t *>(wsb);
+    wsb += align256((size_t)nb * 8);
+    int32_t *bfr = reinterpret_cast<int32_t *>(wsb);
+    wsb += align256((size_t)nb * 4);
+    uint32_t *maxwords = reinterpret_cast<uint32_t *>(wsb);
+    wsb += align256(4);
+    ParCtl *ctl = reinterpret_cast<ParCtl *>(wsb);
+    wsb += align256(sizeof(ParCtl));
+    int64_t *S_cand = reinterpret_cast<int64_t *>(wsb);
+    wsb += align256((size_t)kParMax * 8);
+    int32_t *S_blk = reinterpret_cast<int32_t *>(wsb);
+    hipStream_t s = as_stream(stream);
+    const int64_t W = (ncols + 63) / 64;
+    const int64_t cwords = nrows * W;
+    const int cus = device_cus();
+    const int zg = (int)std::min<int64_t>((cwords + 255) / 256, (int64_t)cus * 16);
+    hipLaunchKernelGGL(greedy_zero, dim3(zg > 0 ? zg : 1), dim3(256), 0, s, cumulative, cwords,
+                       maxwords);
+    if ((rc = check_launch("greedy_zero")) != SITING_OK)
+        return rc;
+    hipLaunchKernelGGL(greedy_init, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, bitmaps,
+                       offsets, obs, n, nrows, ncols, key, fresh);
+    if ((rc = check_launch("greedy_init")) != SITING_OK)
+        return rc;
+    hipLaunchKernelGGL(greedy_blocks, dim3((unsigned)nb), dim3(64), 0, s, key, fresh, obs, n,
+                       nrows, ncols, bmax, bfr, maxwords);
+    if ((rc = check_launch("greedy_blocks")) != SITING_OK)
+        return rc;
+    hipLaunchKernelGGL(gpar_init, dim3(1), dim3(1), 0, s, ctl, max_obs, target_cells);
+    if ((rc = check_launch("gpar_init")) != SITING_OK)
+        return rc;
+    // rounds are enqueued in growing batches; every kernel of a round after
+    // the end returns at once.  Each round selects or makes a stale top exact,
+    // so at most (n + 1) rounds pass between two selections.
+    const int64_t max_rounds = ((int64_t)max_obs + 1) * (n + 1);
+    int64_t rounds = 0;
+    int chunk = 32;
+    for (;;) {
+        for (int r = 0; r < chunk; r++) {
+            hipLaunchKernelGGL(gpar_select, dim3(1), dim3(1024), 0, s, bmax, nb, ctl, S_cand,
+                               S_blk, (int)batch);
+            hipLaunchKernelGGL(gpar_eval, dim3((unsigned)batch), dim3(256), 0, s, bitmaps, offsets,
+                               obs, n, nrows, ncols, cumulative, key, fresh, ctl, S_cand, S_blk,
+                               bmax, bfr);
+            hipLaunchKernelGGL(gpar_decide, dim3(1), dim3(1024), 0, s, key, fresh, bmax, bfr, nb,
+                               n, max_obs, target_cells, ctl, selected, gains);
+            hipLaunchKernelGGL(gpar_or, dim3((unsigned)(cus * 2)), dim3(256), 0, s, bitmaps,
+                               offsets, obs, nrows, ncols, cumulative, ctl);
+        }
+        if ((rc = check_launch("gpar round")) != SITING_OK)
+            return rc;
+        rounds += chunk;
+        int32_t done = 0;
+        SITING_HIP(hipMemcpyAsync(&done, &ctl->done, sizeof(done), hipMemcpyDeviceToHost, s));
+        SITING_HIP(hipStreamSynchronize(s));
+        if (done)
+            break;
+        if (rounds > max_rounds) {
+            set_error("%s: no end after %lld rounds", fn, (long long)rounds);
+            return SITING_E_INTERNAL;
+        }
+        chunk = std::min(chunk * 2, 512);
+    }
+    hipLaunchKernelGGL(gpar_finish, dim3(1), dim3(1), 0, s, ctl, nselected);
+    return check_launch("gpar_finish");
 }
 
 // Device address of `scratch` on the current device, looked up once per

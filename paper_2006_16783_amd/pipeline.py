@@ -35,6 +35,7 @@ class SitingConfig:
     target_frac: float     # SITE coverage target (fraction of all posts)
     vix_seed: int = 12345
     intervisible: bool = False  # SITE: every pick after the first seen by an earlier one
+    site_batch: int | None = None  # SITE rounds over the GPU with this batch (None: by ROI)
 
     def to_dict(self):
         return asdict(self)
@@ -82,6 +83,19 @@ class SitingResult:
     key: object = None
     bitmaps: object = None
     cumulative: object = None
+
+
+def site_batch(cfg: SitingConfig) -> int:
+    """SITE's parallel-round batch for the workload, 0 for one-workgroup rounds.
+    Windows above one wavefront batch (ROI from 128) are evaluated faster by
+    many workgroups per round (measured: ROI 200 147 -> 66 ms, ROI 1000
+    24.8 -> 0.63 s); at ROI 100 one workgroup is faster (17.6 against 75 ms).
+    Intervisibility runs in the one-workgroup kernel."""
+    if cfg.site_batch is not None:
+        return cfg.site_batch
+    if cfg.intervisible or cfg.roi < 128:
+        return 0
+    return 512 if cfg.roi >= 500 else 256
 
 
 def target_cells(frac: float, nrows: int, ncols: int) -> int:
@@ -237,7 +251,8 @@ def run(z, cfg: SitingConfig, key=None, key_stride=1, sched=None, timing=True,
     T.mark("site")
     sel, gains, nsel, cum = L.siting_greedy(bm, off_d, obs_d, nrows, ncols, cfg.max_obs,
                                             target_cells(cfg.target_frac, nrows, ncols),
-                                            intervisible=cfg.intervisible)
+                                            intervisible=cfg.intervisible,
+                                            parallel=site_batch(cfg))
     T.mark("d2h")
     m = int(nsel.item())
     sel_h = sel[:m].cpu().numpy()

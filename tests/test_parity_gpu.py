@@ -399,6 +399,32 @@ def test_greedy_intervisible_chain_on_flat_terrain(S, orc):
     assert int(nsel.item()) == 3 and sel[:3].cpu().tolist() == [0, 1, 2]
 
 
+@pytest.mark.parametrize("seed,nr,nc,n_obs,roi,max_obs,batch", [
+    (81, 1300, 1210, 150, (400, 600), 60, 1),     # one re-evaluation per round
+    (81, 1300, 1210, 150, (400, 600), 60, 7),
+    (82, 900, 870, 700, (5, 300), 250, 64),       # small and large windows
+    (83, 500, 500, 2500, (20, 90), 400, 1024),    # more blocks than one batch holds
+])
+def test_greedy_parallel_parity(S, orc, seed, nr, nc, n_obs, roi, max_obs, batch):
+    # rounds spread over the GPU: the same selection, gains and cumulative
+    # viewshed as the oracle's greedy on its own bitmaps, whatever the batch
+    _say("greedy parallel", seed, nr, nc, n_obs, roi, max_obs, batch)
+    from synth import uniform_observers
+    z = _terrain(nr, 2.4, 1500, seed, ncols=nc)
+    obs = uniform_observers(nr, nc, n_obs, seed, roi=roi, height=(5, 60))
+    bm_h, off = orc.viewshed(z, obs)
+    wsel, wgain, wcum, _ = orc.greedy(bm_h, off, obs, nr, nc, max_obs, nr * nc, lazy=True)
+    bm = torch.from_numpy(bm_h.view(np.int64)).cuda()
+    sel, gains, nsel, cum = S.siting_greedy(bm, torch.from_numpy(off).cuda(),
+                                            S.observers_to_device(obs), nr, nc, max_obs, nr * nc,
+                                            parallel=batch)
+    m = int(nsel.item())
+    assert m == len(wsel)
+    assert (sel[:m].cpu().numpy() == wsel).all()
+    assert (gains[:m].cpu().numpy() == wgain).all()
+    assert (_u64(cum).reshape(-1) == wcum.reshape(-1)).all()
+
+
 def test_greedy_ties_on_flat_terrain(S, orc):
     # flat terrain: equal disks everywhere.  Observers on a lattice of spacing
     # 2R+1 never overlap, so every round is a tie among all unselected ones
