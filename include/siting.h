@@ -67,7 +67,11 @@ typedef struct {
                                terrain in LDS (one half-window at a time);
                                larger ones read the terrain through the cache
                                hierarchy. 0 = none */
-    int32_t reserved;       /* must be 0 */
+    int32_t ray_per_wave;   /* 0: one ray per lane; 1: one wavefront per ray
+                               (64 samples of the ray at a time, the horizon
+                               as an exact prefix maximum across lanes), for
+                               the observers whose terrain is read from global
+                               memory (not staged); same bits either way */
 } siting_schedule;
 
 enum { SITING_KEY_U8 = 0, SITING_KEY_F32 = 1 };

@@ -33,13 +33,14 @@ class SitingError(RuntimeError):
 
 class Schedule(C.Structure):
     _fields_ = [("waves", C.c_int32), ("groups_per_cu", C.c_int32),
-                ("stage_rmax", C.c_int32), ("reserved", C.c_int32)]
+                ("stage_rmax", C.c_int32), ("ray_per_wave", C.c_int32)]
 
     def as_tuple(self):
-        return (self.waves, self.groups_per_cu, self.stage_rmax)
+        return (self.waves, self.groups_per_cu, self.stage_rmax, self.ray_per_wave)
 
     def __repr__(self):
-        return "Schedule(waves=%d, groups_per_cu=%d, stage_rmax=%d)" % self.as_tuple()
+        return ("Schedule(waves=%d, groups_per_cu=%d, stage_rmax=%d, ray_per_wave=%d)"
+                % self.as_tuple())
 
 
 def _load():

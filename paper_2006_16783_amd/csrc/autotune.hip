@@ -66,12 +66,21 @@ extern "C" int siting_autotune_candidates(int32_t rmax, siting_schedule *out_hos
                 bool dup = false;
                 for (auto &e : c)
                     dup |= e.waves == s.waves && e.groups_per_cu == s.groups_per_cu &&
-                           e.stage_rmax == s.stage_rmax;
+                           e.stage_rmax == s.stage_rmax && e.ray_per_wave == s.ray_per_wave;
                 if (!dup)
                     c.push_back(s);
             }
         }
     }
+    // where observers read their terrain from global memory (staging below
+    // rmax), the same schedule with one wavefront per ray as well
+    const size_t nlane = c.size();
+    for (size_t e = 0; e < nlane; e++)
+        if (c[e].stage_rmax < rmax && c[e].waves >= 4) {
+            siting_schedule w = c[e];
+            w.ray_per_wave = 1;
+            c.push_back(w);
+        }
     int m = std::min<int>((int)c.size(), max_out);
     for (int i = 0; i < m; i++)
         out_host[i] = c[i];
@@ -95,13 +104,13 @@ extern "C" int siting_autotune(const int16_t *z, int64_t nrows, int64_t ncols, i
         set_error("%s: workspace too small", fn);
         return SITING_E_WORKSPACE;
     }
-    siting_schedule cand[64];
-    int nc = siting_autotune_candidates(rmax, cand, 64);
+    siting_schedule cand[128];
+    int nc = siting_autotune_candidates(rmax, cand, 128);
     if (nc <= 0) {
         set_error("%s: no schedule fits rmax %d", fn, rmax);
         return SITING_E_UNSUPPORTED;
     }
-    nc = std::min(nc, 64);
+    nc = std::min(nc, 128);
     hipStream_t s = as_stream(stream);
     hipEvent_t e0, e1;
     SITING_HIP(hipEventCreate(&e0));

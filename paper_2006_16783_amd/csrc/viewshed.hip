@@ -184,6 +184,113 @@ __device__ __forceinline__ void sweep(const Src &src, int zs_u, int zs_v, uint32
     }
 }
 
+// One wavefront per ray (schedule ray_per_wave): the ray's samples are taken
+// 64 at a time, sample k = 64c + lane + 1 on lane `lane` of chunk c, all with
+// the same comparisons as sweep().  The horizon before sample k is the
+// largest terrain slope T_j / j over j < k; the wavefront gets it as an
+// exact prefix maximum of the rational slopes across lanes (DPP scan,
+// cross-multiplied in int64; k == 0 marks "no sample"), shifted by one lane
+// and combined with the maximum carried from earlier chunks.  Each lane
+// advances its crossing (q, r) by 64 samples per chunk without division.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ int dpp32(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, kCtrl, kRowMask, 0xF, false);
+}
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ void scan_step(long long &T, int &k)
+{
+    const int lo = dpp32<kCtrl, kRowMask>((int)(uint32_t)(unsigned long long)T);
+    const int hi = dpp32<kCtrl, kRowMask>((int)(uint32_t)((unsigned long long)T >> 32));
+    const long long oT = (long long)(((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo);
+    const int ok = dpp32<kCtrl, kRowMask>(k);
+    if (ok != 0 && (k == 0 || oT * k > T * ok)) {
+        T = oT;
+        k = ok;
+    }
+}
+
+template <bool kGuardZ1, class Src>
+__device__ __forceinline__ void sweep_wave(const Src &src, int zs_u, int zs_v, uint32_t *bm,
+                                           int P0, int bu, int bv, int du, int dv, int R2, int E,
+                                           int h_r, int lane)
+{
+    const bool umaj = du >= dv;
+    const int n = umaj ? du : dv, mn = umaj ? dv : du;
+    const int zs_maj = umaj ? zs_u : zs_v, zs_min = umaj ? zs_v : zs_u;
+    const int bs_maj = umaj ? bu : bv, bs_min = umaj ? bv : bu;
+    const long long En = (long long)E * n, hrn = (long long)h_r * n;
+    // crossing of sample k = lane + 1, and the advance of 64 samples
+    int k = lane + 1;
+    int q = (int)((uint32_t)(k * mn) / (uint32_t)n);
+    int r = k * mn - q * n;
+    const int dq = (int)((uint32_t)(64 * mn) / (uint32_t)n), dr = 64 * mn - dq * n;
+    long long cT = 0;  // horizon carried from earlier chunks (ck == 0: none yet)
+    int ck = 0;
+    for (;;) {
+        const int up = 2 * r >= n ? 1 : 0;
+        const int m = q + up;
+        const bool inside = k <= n && k * k + m * m <= R2;
+        // the marked cells leave the disk for good: done when the chunk's
+        // first sample is outside
+        if (!(__ballot(inside) & 1ull))
+            break;
+        long long T = 0;
+        if (inside) {
+            const int zi = k * zs_maj + q * zs_min;
+            const int z0 = src.at(zi);
+            const int z1 = (!kGuardZ1 || r) ? src.at(zi + zs_min) : 0;
+            T = (long long)z0 * (n - r) + (long long)z1 * r - En;
+        }
+        // inclusive prefix maximum of the slopes T / k over the chunk
+        long long sT = T;
+        int sk = inside ? k : 0;
+        scan_step<0x111, 0xF>(sT, sk);
+        scan_step<0x112, 0xF>(sT, sk);
+        scan_step<0x114, 0xF>(sT, sk);
+        scan_step<0x118, 0xF>(sT, sk);
+        scan_step<0x142, 0xA>(sT, sk);
+        scan_step<0x143, 0xC>(sT, sk);
+        // exclusive: the previous lane's, then the carried horizon
+        long long eT = (long long)(((unsigned long long)(uint32_t)__shfl_up(
+                                        (int)(uint32_t)((unsigned long long)sT >> 32), 1, 64)
+                                    << 32) |
+                                   (uint32_t)__shfl_up((int)(uint32_t)(unsigned long long)sT, 1, 64));
+        int ek = __shfl_up(sk, 1, 64);
+        if (lane == 0) {
+            eT = 0;
+            ek = 0;
+        }
+        if (ck != 0 && (ek == 0 || cT * ek > eT * ck)) {
+            eT = cT;
+            ek = ck;
+        }
+        // the first sample of the ray has no horizon and is visible
+        if (inside && (ek == 0 || (T + hrn) * ek >= eT * k)) {
+            const int bp = P0 + k * bs_maj + m * bs_min;
+            atomicOr(&bm[bp >> 5], 1u << (bp & 31));
+        }
+        // carry the chunk's maximum (lane 63 holds the inclusive maximum)
+        const int tk = __builtin_amdgcn_readlane(sk, 63);
+        const long long tT = (long long)(((unsigned long long)(uint32_t)__builtin_amdgcn_readlane(
+                                              (int)(uint32_t)((unsigned long long)sT >> 32), 63)
+                                          << 32) |
+                                         (uint32_t)__builtin_amdgcn_readlane(
+                                             (int)(uint32_t)(unsigned long long)sT, 63));
+        if (tk != 0 && (ck == 0 || tT * ck > cT * tk)) {
+            cT = tT;
+            ck = tk;
+        }
+        k += 64;
+        q += dq;
+        r += dr;
+        if (r >= n) {
+            r -= n;
+            q++;
+        }
+    }
+}
+
 // 24-bit signed multiply-add (full rate): a * b + c with |a|, |b| < 2^23.
 __device__ __forceinline__ int mad_i24(int a, int b, int c)
 {
@@ -385,7 +492,7 @@ __global__ void viewshed_kernel(const int16_t *__restrict__ z, int64_t nrows, in
                                 const int32_t *__restrict__ order, int sink,
                                 uint64_t *__restrict__ bitmaps, uint32_t *__restrict__ visible,
                                 uint32_t *__restrict__ cells, uint32_t *queue, int rmax,
-                                int stage_rmax, int dma, int mode)
+                                int stage_rmax, int dma, int mode, int ray_wave)
 {
     // mode 0: window bitmap in LDS; 1: quadrant mode; 2: global-bitmap mode
     const int quad = mode == 1;
@@ -458,13 +565,19 @@ __global__ void viewshed_kernel(const int16_t *__restrict__ z, int64_t nrows, in
             const int n2 = n1 + (ex_m >= 1 ? ex_m + ey_m : 0);
             const int n3 = n2 + (ey_m >= 1 ? ey_m + ex_p : 0);
             GlobalSrc src{zo};
-            for (int rho = tid; rho < n3; rho += nthreads) {
+            const int r0 = ray_wave ? wave : tid, rs = ray_wave ? nwaves : nthreads;
+            for (int rho = r0; rho < n3; rho += rs) {
                 const int qd = rho < n0 ? 0 : rho < n1 ? 1 : rho < n2 ? 2 : 3;
                 const int base = qd == 0 ? 0 : qd == 1 ? n0 : qd == 2 ? n1 : n2;
                 const Quadrant Q = make_quadrant(qd, ex_p, ex_m, ey_p, ey_m, GP, (int)ld);
                 int du, dv;
                 ray_target(Q, rho - base, du, dv);
-                sweep<false, true>(src, Q.gu, Q.gv, gbm, P0g, Q.bu, Q.bv, du, dv, R2, E, o.h_r);
+                if (ray_wave)
+                    sweep_wave<true>(src, Q.gu, Q.gv, gbm, P0g, Q.bu, Q.bv, du, dv, R2, E, o.h_r,
+                                     lane);
+                else
+                    sweep<false, true>(src, Q.gu, Q.gv, gbm, P0g, Q.bu, Q.bv, du, dv, R2, E,
+                                       o.h_r);
             }
             __threadfence();
             __syncthreads();
@@ -533,11 +646,16 @@ __global__ void viewshed_kernel(const int16_t *__restrict__ z, int64_t nrows, in
                     atomicOr(&bm[P0q >> 5], 1u << (P0q & 31));
                 const Quadrant Q = make_quadrant(qd, ex_p, ex_m, ey_p, ey_m, QP, (int)ld);
                 const int nrays = Q.eu >= 1 ? Q.eu + Q.ev : 0;
-                for (int rho = tid; rho < nrays; rho += nthreads) {
+                const int q0 = ray_wave ? wave : tid, qs = ray_wave ? nwaves : nthreads;
+                for (int rho = q0; rho < nrays; rho += qs) {
                     int du, dv;
                     ray_target(Q, rho, du, dv);
-                    sweep<false, true>(src, Q.gu, Q.gv, bm, P0q, Q.bu, Q.bv, du, dv, R2, E,
-                                       o.h_r);
+                    if (ray_wave)
+                        sweep_wave<true>(src, Q.gu, Q.gv, bm, P0q, Q.bu, Q.bv, du, dv, R2, E,
+                                         o.h_r, lane);
+                    else
+                        sweep<false, true>(src, Q.gu, Q.gv, bm, P0q, Q.bu, Q.bv, du, dv, R2, E,
+                                           o.h_r);
                 }
                 __syncthreads();
                 if (sink == SITING_SINK_BITMAP) {
@@ -766,13 +884,18 @@ __global__ void viewshed_kernel(const int16_t *__restrict__ z, int64_t nrows, in
             int n2 = n1 + (ex_m >= 1 ? ex_m + ey_m : 0);
             int n3 = n2 + (ey_m >= 1 ? ey_m + ex_p : 0);
             GlobalSrc src{zo};
-            for (int rho = tid; rho < n3; rho += nthreads) {
+            const int r0 = ray_wave ? wave : tid, rs = ray_wave ? nwaves : nthreads;
+            for (int rho = r0; rho < n3; rho += rs) {
                 int qd = rho < n0 ? 0 : rho < n1 ? 1 : rho < n2 ? 2 : 3;
                 int base = qd == 0 ? 0 : qd == 1 ? n0 : qd == 2 ? n1 : n2;
                 Quadrant Q = make_quadrant(qd, ex_p, ex_m, ey_p, ey_m, BP, (int)ld);
                 int du, dv;
                 ray_target(Q, rho - base, du, dv);
-                sweep<false, true>(src, Q.gu, Q.gv, bm, P0, Q.bu, Q.bv, du, dv, R2, E, o.h_r);
+                if (ray_wave)
+                    sweep_wave<true>(src, Q.gu, Q.gv, bm, P0, Q.bu, Q.bv, du, dv, R2, E, o.h_r,
+                                     lane);
+                else
+                    sweep<false, true>(src, Q.gu, Q.gv, bm, P0, Q.bu, Q.bv, du, dv, R2, E, o.h_r);
             }
             __syncthreads();
         }
@@ -880,14 +1003,14 @@ int viewshed_launch(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
     const int dma = ld % 2 == 0 && ncols % 2 == 0 && reinterpret_cast<uintptr_t>(z) % 4 == 0;
     hipLaunchKernelGGL(viewshed_kernel, dim3((unsigned)grid), dim3(64 * sc.waves), (size_t)lds, s,
                        z, nrows, ncols, ld, obs, n, offsets, order, sink, bitmaps, visible, cells,
-                       queue, rmax, stage, dma, mode);
+                       queue, rmax, stage, dma, mode, sc.ray_per_wave);
     return check_launch("viewshed_kernel");
 }
 
 int viewshed_default_schedule(int32_t rmax, siting_schedule *sc)
 {
     const int budget = 160 * 1024;
-    sc->reserved = 0;
+    sc->ray_per_wave = 0;
     int lds_staged = lds_bytes_for(rmax, rmax);
     if (rmax <= 160 && lds_staged <= std::min(budget, viewshed_max_dynamic_lds())) {
         // a half-window has about 4R rays: enough wavefronts to sweep them in
@@ -927,7 +1050,8 @@ int validate_schedule(const siting_schedule &sc, const char *fn)
                    "%s: schedule groups_per_cu %d outside 1..16", fn, sc.groups_per_cu);
     SITING_REQUIRE(sc.stage_rmax >= 0 && sc.stage_rmax <= kMaxRoi,
                    "%s: schedule stage_rmax out of range", fn);
-    SITING_REQUIRE(sc.reserved == 0, "%s: schedule reserved field must be 0", fn);
+    SITING_REQUIRE(sc.ray_per_wave == 0 || sc.ray_per_wave == 1,
+                   "%s: schedule ray_per_wave must be 0 or 1", fn);
     return SITING_OK;
 }
 

@@ -60,7 +60,8 @@ def autotune_cached(z, obs_dev, offsets_dev, rmax, bitmaps, path, order_dev=None
     hit = data.get(key)
     if hit is not None:
         s = Schedule()
-        s.waves, s.groups_per_cu, s.stage_rmax = (int(v) for v in hit["schedule"])
+        v = [int(x) for x in hit["schedule"]] + [0]  # (entries without ray_per_wave: 0)
+        s.waves, s.groups_per_cu, s.stage_rmax, s.ray_per_wave = v[:4]
         return s, True
     tune = tune or siting_autotune
     best, times = tune(z, obs_dev, offsets_dev, rmax, bitmaps, order_dev=order_dev)

@@ -134,7 +134,7 @@ def test_schedule_cache_round_trip(tmp_path):
     s1, hit1 = SC.autotune_cached(z, obs, None, 90, None, path, tune=tune)
     s2, hit2 = SC.autotune_cached(z, obs, None, 90, None, path, tune=tune)
     assert (hit1, hit2) == (False, True) and calls == [90]
-    assert s1.as_tuple() == s2.as_tuple() == (8, 3, 90)
+    assert s1.as_tuple() == s2.as_tuple() == (8, 3, 90, 0)
     # another batch bucket or ROI maximum is tuned again
     SC.autotune_cached(z, torch.zeros((300, 5), dtype=torch.int32), None, 90, None, path, tune=tune)
     SC.autotune_cached(z, obs, None, 120, None, path, tune=tune)

@@ -271,6 +271,37 @@ def test_viewshed_every_schedule_same_bits(S, orc):
         assert (got == want).all(), sc
 
 
+@pytest.mark.parametrize("seed,roi,shape,relief", [
+    (91, (150, 400), (900, 870), 2000),      # terrain read from global memory, bitmap in LDS
+    (92, (60, 120), (260, 270), None),       # extreme relief (int64 slopes)
+    (93, (560, 800), (1300, 1250), 2500),    # quadrant mode
+    (94, (1100, 1600), (3300, 3200), 2700),  # global-bitmap mode
+])
+def test_viewshed_ray_per_wave(S, orc, seed, roi, shape, relief):
+    # one wavefront per ray (64 samples at a time, the horizon as a prefix
+    # maximum across lanes): the same bits as the oracle, edge windows included
+    _say("viewshed ray per wave", seed, roi, shape)
+    nr, nc = shape
+    if relief is None:
+        z = np.random.default_rng(seed).integers(-32768, 32767, size=shape).astype(np.int16)
+        height = (0, 32767)
+    else:
+        z = _terrain(nr, 2.4, relief, seed, ncols=nc)
+        height = (5, 100)
+    obs = _quadrant_observers(nr, nc, 24, seed, roi, height)
+    sc = S.Schedule(16, 1, 0, 1)
+    got, want = _viewshed_case(S, orc, z, obs, roi[1], sched=sc)
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, ("viewshed words differ", bad[:8])
+    if roi[1] <= 1087:
+        vis, cells = S.siting_viewshed_batch(torch.from_numpy(z).cuda(),
+                                             S.observers_to_device(obs), None, roi[1],
+                                             sched=sc, sink=S.SITING_SINK_COUNT)
+        wv, wc = orc.viewshed_count(z, obs)
+        assert (vis.cpu().numpy().astype(np.uint32) == wv).all()
+        assert (cells.cpu().numpy().astype(np.uint32) == wc).all()
+
+
 def test_viewshed_wide_arithmetic(S, orc):
     # extreme relief forces the int64 comparison path
     rng = np.random.default_rng(0)

@@ -35,6 +35,20 @@ def S():
     return S
 
 
+@pytest.fixture(autouse=True)
+def _release_device_memory():
+    # each workload holds up to ~200 GB of window bitmaps: hand torch's cached
+    # segments back before and after every test, so that a later workload
+    # does not carve its terrain out of an earlier one's bitmap segment and
+    # then find no room for its own bitmaps
+    import gc
+    gc.collect()
+    torch.cuda.empty_cache()
+    yield
+    gc.collect()
+    torch.cuda.empty_cache()
+
+
 def _u64(t):
     return t.cpu().numpy().view(np.uint64)
 
