@@ -1,7 +1,9 @@
 // Learned ranking: a small CNN that predicts a post's visibility index from
 // the 64 x 64 terrain patch around it, used only as an alternative FINDMAX
 // key.  Forward, backward and Adam are all here; convolutions run on MFMA
-// (v_mfma_f32_16x16x16_bf16: bf16 operands, fp32 accumulation).
+// (bf16 operands, fp32 accumulation: v_mfma_f32_16x16x16_bf16 for conv1 and
+// the backward GEMMs, gfx950's v_mfma_f32_16x16x32_bf16 for the forward
+// conv2 and conv3).
 //
 // Network (patch of 64 x 64 posts around the post):
 //   input  P = bf16(float(z[clamped post] - z[centre]) * 2^-8)    64 x 64
@@ -15,10 +17,11 @@
 // MFMA 16x16x16 operand layout (per lane l of a wavefront): A supplies row
 // l%16, k = 4*(l/16)..+3; B supplies column l%16, k = 4*(l/16)..+3; the
 // accumulator holds column l%16, rows 4*(l/16)..+3.  The 4x4 stride-4 first
-// layer is chosen so that an A fragment is exactly 4 contiguous posts of one
-// patch row (no im2col); conv2/conv3 fragments are 4 contiguous channels of
-// one input position.
+// layer is chosen so that a patch fragment is exactly 4 contiguous posts of
+// one patch row (no im2col); the forward conv2/conv3 fragments (16x16x32,
+// k = 8*(l/16)..+7) are 8 contiguous channels of one input position.
 #include <algorithm>
+#include <type_traits>
 
 #include "common.hpp"
 
@@ -26,18 +29,22 @@ namespace siting {
 namespace {
 
 typedef short s4 __attribute__((ext_vector_type(4)));
+typedef short s8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u2v __attribute__((ext_vector_type(2)));
+typedef uint32_t u4v __attribute__((ext_vector_type(4)));
 
 // parameter offsets in the flat fp32 vector
 constexpr int OW1 = 0, OB1 = 256, OW2 = 272, OB2 = 2576, OW3 = 2592, OB3 = 7200, OWFC = 7232,
               OBFC = 7264, NPARAMS = 7265;
 constexpr int kPatch = 64;
 constexpr int kFwdWaves = 4;
-// LDS pitch of one activation position: 16 channels padded to 18 bf16
-// (36 bytes), so that the 4-channel fragments of positions two apart, which
-// the 3x3 stride-2 layers read side by side, fall in different banks
-constexpr int kPosPitch = 18;
-constexpr int kWaveLdsElems = 256 * kPosPitch + 64 * kPosPitch;
+// per-wavefront LDS: conv1 and conv2 activations, 16-byte entries of 8
+// bf16 channels (two entries per position)
+constexpr int kH1Bytes = 2 * 256 * 16;
+constexpr int kH2Bytes = 2 * 64 * 16;
+constexpr int kWaveLdsBytes = kH1Bytes + kH2Bytes;
 
 __device__ __forceinline__ short bf16_bits(float f)
 {
@@ -48,14 +55,27 @@ __device__ __forceinline__ float bf16_float(uint16_t b)
 {
     return __uint_as_float((uint32_t)b << 16);
 }
+typedef float f2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+typedef short sh2 __attribute__((ext_vector_type(2)));
+// two floats to two bf16 (round to nearest even) in one packed conversion
+__device__ __forceinline__ uint32_t pk_bf16(float a, float b)
+{
+    const bf2 h = __builtin_convertvector(f2{a, b}, bf2);
+    return __builtin_bit_cast(uint32_t, h);
+}
 __device__ __forceinline__ s4 pack4(float a, float b, float c, float d)
 {
-    s4 r;
-    r.x = bf16_bits(a);
-    r.y = bf16_bits(b);
-    r.z = bf16_bits(c);
-    r.w = bf16_bits(d);
-    return r;
+    const uint32_t lo = pk_bf16(a, b), hi = pk_bf16(c, d);
+    return __builtin_bit_cast(s4, (uint64_t)lo | ((uint64_t)hi << 32));
+}
+// ReLU of two bf16 given as bits: a negative bf16 (sign bit set) is a
+// negative int16, so a packed int16 maximum with 0 zeroes it and keeps the
+// rest (ReLU then rounding equals rounding then ReLU)
+__device__ __forceinline__ uint32_t relu_bf16x2(uint32_t v)
+{
+    const sh2 x = __builtin_bit_cast(sh2, v);
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(x, sh2{0, 0}));
 }
 // Orders this wavefront's LDS writes before its later LDS reads by other
 // lanes of the same wavefront.
@@ -66,17 +86,17 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// 4 consecutive bf16 at a 4-byte aligned LDS address (two dword reads)
-__device__ __forceinline__ s4 lds_frag(const uint16_t *p)
+// 8 consecutive bf16 at a 16-byte aligned LDS address (one 16-byte read,
+// taken as the fragment's bits unchanged)
+__device__ __forceinline__ s8 lds_frag8(const unsigned char *p)
 {
-    const uint32_t *q = reinterpret_cast<const uint32_t *>(p);
-    const uint32_t u0 = q[0], u1 = q[1];
-    s4 r;
-    r.x = (short)(u0 & 0xFFFFu);
-    r.y = (short)(u0 >> 16);
-    r.z = (short)(u1 & 0xFFFFu);
-    r.w = (short)(u1 >> 16);
-    return r;
+    return __builtin_bit_cast(s8, *reinterpret_cast<const u4v *>(p));
+}
+// 8 consecutive fp32 weights as a bf16 fragment
+__device__ __forceinline__ s8 pack8(const float *w)
+{
+    return __builtin_bit_cast(s8, u4v{pk_bf16(w[0], w[1]), pk_bf16(w[2], w[3]),
+                                      pk_bf16(w[4], w[5]), pk_bf16(w[6], w[7])});
 }
 
 // wavefront max of non-negative ints and sum of floats on DPP row moves
@@ -107,6 +127,13 @@ __device__ __forceinline__ f4 mfma(s4 a, s4 b, f4 c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
+// gfx950's double-K form: per lane k = 8*(l/16)..+7 of A's row l%16 and of
+// B's column l%16; the accumulator layout is the 16x16x16 one
+__device__ __forceinline__ f4 mfma32(s8 a, s8 b, f4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a),
+                                                   __builtin_bit_cast(bf8, b), c, 0, 0, 0);
+}
 
 // ----------------------------------------------------------------- forward
 // One wavefront per post.  kTrain: posts are given centres and every
@@ -130,43 +157,85 @@ struct FwdArgs {
 };
 
 template <bool kTrain>
-__global__ __launch_bounds__(64 * kFwdWaves) void cnn_fwd_kernel(FwdArgs A)
+__global__ __launch_bounds__(64 * kFwdWaves) __attribute__((amdgpu_waves_per_eu(2, 2))) void
+cnn_fwd_kernel(FwdArgs A)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lane = threadIdx.x & 63;
+    // the wavefront index as a uniform value: per-post bookkeeping (cell,
+    // highest post, patch origin) then stays in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lo = lane & 15, hi = lane >> 4;
-    // per-wave activations: H1 [256 pos][16 ch] bf16, H2 [64 pos][16 ch]
-    uint16_t *H1 = reinterpret_cast<uint16_t *>(smem) + wave * kWaveLdsElems;
-    uint16_t *H2 = H1 + 256 * kPosPitch;
-    int16_t *tile = reinterpret_cast<int16_t *>(smem + kFwdWaves * kWaveLdsElems * 2);
+    // per-wavefront activations in 16-byte entries of 8 channels:
+    //   H1 [chunk 2][row 16][column 16: even columns, then odd] (8 KB)
+    //   H2 [chunk 2][position 64] (2 KB; positions 49..63 unused)
+    // chunk c holds channels 8c..8c+7.  An x32 fragment is one entry; the
+    // 3x3 stride-2 conv2 reads input columns 2tx+kx, which this column
+    // order makes consecutive in tx.
+    unsigned char *H1 = smem + wave * kWaveLdsBytes;
+    unsigned char *H2 = H1 + kH1Bytes;
+    int16_t *tile = reinterpret_cast<int16_t *>(smem + kFwdWaves * kWaveLdsBytes);
 
-    // weights as B fragments (bf16) and per-lane biases.  Scoring moves the
+    // weights as bf16 fragments and per-lane biases.  Scoring moves the
     // input's 2^-8 scale into w1: a power-of-two factor commutes with bf16
     // rounding and with the exact products, so the accumulators are the same
     // bits (training keeps the scaled patch, which its backward pass reads).
+    // conv1 and conv2 run transposed (weights as the row operand, channels x
+    // positions); conv3 runs positions x channels.  An x32 fragment spans two
+    // taps: lanes with hi < 2 take tap 2j, the others tap 2j+1 (tap 9 is a
+    // zero weight read over tap 8's activations).
     const float *p = A.params;
     const float w1s = kTrain ? 1.0f : 0.00390625f;
-    s4 bw1 = pack4(p[OW1 + lo * 16 + hi * 4 + 0] * w1s, p[OW1 + lo * 16 + hi * 4 + 1] * w1s,
-                   p[OW1 + lo * 16 + hi * 4 + 2] * w1s, p[OW1 + lo * 16 + hi * 4 + 3] * w1s);
-    s4 bw2[9], bw3[9][2];
+    const s4 bw1 = pack4(p[OW1 + lo * 16 + hi * 4 + 0] * w1s, p[OW1 + lo * 16 + hi * 4 + 1] * w1s,
+                         p[OW1 + lo * 16 + hi * 4 + 2] * w1s, p[OW1 + lo * 16 + hi * 4 + 3] * w1s);
+    const int half = hi >> 1, ci0 = 8 * (hi & 1);
+    s8 aw2[5], bw3[5][2];
 #pragma unroll
-    for (int t = 0; t < 9; t++) {
-        const float *w = p + OW2 + lo * 144 + t * 16 + hi * 4;
-        bw2[t] = pack4(w[0], w[1], w[2], w[3]);
+    for (int j = 0; j < 5; j++) {
+        const int tap = 2 * j + half;
+        const bool real = tap < 9;
+        aw2[j] = real ? pack8(p + OW2 + lo * 144 + tap * 16 + ci0) : s8{};
 #pragma unroll
-        for (int nt = 0; nt < 2; nt++) {
-            const float *u = p + OW3 + (nt * 16 + lo) * 144 + t * 16 + hi * 4;
-            bw3[t][nt] = pack4(u[0], u[1], u[2], u[3]);
-        }
+        for (int nt = 0; nt < 2; nt++)
+            bw3[j][nt] = real ? pack8(p + OW3 + (nt * 16 + lo) * 144 + tap * 16 + ci0) : s8{};
     }
-    const float b2 = p[OB2 + lo];
-    // conv1 runs transposed (channels x positions): a lane holds channels
-    // 4hi..4hi+3 of one position
-    const float b1q[4] = {p[OB1 + 4 * hi], p[OB1 + 4 * hi + 1], p[OB1 + 4 * hi + 2],
-                          p[OB1 + 4 * hi + 3]};
+    const f4 b1v = {p[OB1 + 4 * hi], p[OB1 + 4 * hi + 1], p[OB1 + 4 * hi + 2], p[OB1 + 4 * hi + 3]};
+    const f4 b2v = {p[OB2 + 4 * hi], p[OB2 + 4 * hi + 1], p[OB2 + 4 * hi + 2], p[OB2 + 4 * hi + 3]};
     const float b3[2] = {p[OB3 + lo], p[OB3 + 16 + lo]};
     const float wfc[2] = {p[OWFC + lo], p[OWFC + 16 + lo]};
     const float bfc = p[OBFC];
+
+    // per-lane LDS byte offsets, the same for every post
+    // conv1 output: channels 4hi..4hi+3 of column lo (row oy adds oy * 256)
+    const uint32_t w1off = ((hi >> 1) * 256 + (lo & 1) * 8 + (lo >> 1)) * 16 + (hi & 1) * 8;
+    // conv2 input: position 16t+lo (clamped to 48) of row tile t, tap of x32 step j
+    uint32_t base2[4], toff2[5];
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+        const int n = 16 * t + lo > 48 ? 48 : 16 * t + lo;
+        const int ty = n / 7, tx = n - ty * 7;
+        base2[t] = ((hi & 1) * 256 + 2 * ty * 16 + tx) * 16;
+    }
+#pragma unroll
+    for (int j = 0; j < 5; j++) {
+        const int tap = 2 * j + half > 8 ? 8 : 2 * j + half;
+        const int ky = tap / 3, kx = tap - 3 * ky;
+        toff2[j] = (ky * 16 + (kx == 1 ? 8 : kx == 2 ? 1 : 0)) * 16;
+    }
+    // conv2 output: channels 4hi..4hi+3 of position 16t+lo (t adds t * 256)
+    const uint32_t w2off = ((hi >> 1) * 64 + lo) * 16 + (hi & 1) * 8;
+    // conv3 input: position min(lo, 8) of the 3 x 3 output, tap of step j
+    uint32_t off3[5];
+    {
+        const int m = lo > 8 ? 8 : lo;
+        const int oy = m / 3, ox = m - oy * 3;
+#pragma unroll
+        for (int j = 0; j < 5; j++) {
+            const int tap = 2 * j + half > 8 ? 8 : 2 * j + half;
+            const int ky = tap / 3, kx = tap - 3 * ky;
+            off3[j] = ((hi & 1) * 64 + (2 * oy + ky) * 7 + 2 * ox + kx) * 16;
+        }
+    }
 
     // tile geometry
     int tw = kPatch, th = kPatch;  // tile width/height in posts
@@ -270,104 +339,103 @@ __global__ __launch_bounds__(64 * kFwdWaves) void cnn_fwd_kernel(FwdArgs A)
         }
         const int zc = tile[(or_ + kPatch / 2) * tp + oc + kPatch / 2];
 
-        // ---- conv1: one MFMA per output row oy (16 output columns)
-#pragma unroll 4
-        for (int oy = 0; oy < 16; oy++) {
-            const int16_t *src = tile + (or_ + 4 * oy + hi) * tp + oc + 4 * lo;
-            // the four posts as two dwords: rows start dword-aligned (tp is a
-            // multiple of 4), so a patch's reads are aligned when oc is even
-            // and otherwise take three dwords shifted by one post
-            uint32_t p01, p23;
-            if ((oc & 1) == 0) {
-                const uint32_t *q = reinterpret_cast<const uint32_t *>(src);
-                p01 = q[0];
-                p23 = q[1];
-            } else {
-                const uint32_t *q = reinterpret_cast<const uint32_t *>(src - 1);
-                const uint32_t d0 = q[0], d1 = q[1], d2 = q[2];
-                p01 = __builtin_amdgcn_alignbyte(d1, d0, 2);
-                p23 = __builtin_amdgcn_alignbyte(d2, d1, 2);
+        // ---- conv1: one MFMA per output row oy (16 output columns).  The
+        // four posts of a fragment are two dwords: rows start dword-aligned
+        // (tp is a multiple of 4), so they are aligned when oc is even and
+        // otherwise take three dwords shifted by one post.
+        // All 16 rows are read before the first H1 write, so that the
+        // compiler may overlap one row's conversion with another's MFMA
+        // (the LDS writes would otherwise order every later read).
+        auto conv1 = [&](auto odd) {
+            constexpr bool kOdd = decltype(odd)::value;
+            const int16_t *src0 = tile + (or_ + hi) * tp + oc + 4 * lo;
+            uint32_t P01[16], P23[16];
+#pragma unroll
+            for (int oy = 0; oy < 16; oy++) {
+                const int16_t *src = src0 + 4 * oy * tp;
+                if (!kOdd) {
+                    const uint32_t *q = reinterpret_cast<const uint32_t *>(src);
+                    P01[oy] = q[0];
+                    P23[oy] = q[1];
+                } else {
+                    const uint32_t *q = reinterpret_cast<const uint32_t *>(src - 1);
+                    const uint32_t d0 = q[0], d1 = q[1], d2 = q[2];
+                    P01[oy] = __builtin_amdgcn_alignbyte(d1, d0, 2);
+                    P23[oy] = __builtin_amdgcn_alignbyte(d2, d1, 2);
+                }
             }
-            // elevation differences in units of 256 m (exact power-of-two scale)
-            constexpr float kScale = kTrain ? 0.00390625f : 1.0f;
-            const float v0 = (float)((int)(int16_t)(p01 & 0xFFFFu) - zc) * kScale;
-            const float v1 = (float)((int)(int16_t)(p01 >> 16) - zc) * kScale;
-            const float v2 = (float)((int)(int16_t)(p23 & 0xFFFFu) - zc) * kScale;
-            const float v3 = (float)((int)(int16_t)(p23 >> 16) - zc) * kScale;
-            const s4 a = pack4(v0, v1, v2, v3);
-            if (kTrain) {
-                uint16_t *ps = A.Pst + pid * 4096 + (4 * oy + hi) * 64 + 4 * lo;
-                ps[0] = (uint16_t)a.x; ps[1] = (uint16_t)a.y;
-                ps[2] = (uint16_t)a.z; ps[3] = (uint16_t)a.w;
+            // four rows at a time: four independent MFMAs in flight
+#pragma unroll
+            for (int g = 0; g < 16; g += 4) {
+                f4 c[4];
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const int oy = g + u;
+                    const uint32_t p01 = P01[oy], p23 = P23[oy];
+                    // elevation differences in units of 256 m (exact
+                    // power-of-two scale)
+                    constexpr float kScale = kTrain ? 0.00390625f : 1.0f;
+                    const float v0 = (float)((int)(int16_t)(p01 & 0xFFFFu) - zc) * kScale;
+                    const float v1 = (float)((int)(int16_t)(p01 >> 16) - zc) * kScale;
+                    const float v2 = (float)((int)(int16_t)(p23 & 0xFFFFu) - zc) * kScale;
+                    const float v3 = (float)((int)(int16_t)(p23 >> 16) - zc) * kScale;
+                    const uint64_t a = (uint64_t)pk_bf16(v0, v1) | ((uint64_t)pk_bf16(v2, v3) << 32);
+                    if (kTrain)
+                        *reinterpret_cast<uint64_t *>(A.Pst + pid * 4096 + (4 * oy + hi) * 64 + 4 * lo) = a;
+                    // the lane gets channels 4hi..4hi+3 of position (oy, lo);
+                    // the bias is the accumulator's initial value
+                    c[u] = mfma(bw1, __builtin_bit_cast(s4, a), b1v);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const int oy = g + u;
+                    // ReLU on the rounded bf16 pairs
+                    const uint32_t h01 = relu_bf16x2(pk_bf16(c[u][0], c[u][1]));
+                    const uint32_t h23 = relu_bf16x2(pk_bf16(c[u][2], c[u][3]));
+                    *reinterpret_cast<u2v *>(H1 + w1off + oy * 256) = u2v{h01, h23};
+                    if (kTrain)
+                        *reinterpret_cast<u2v *>(A.H1st + (pid * 256 + oy * 16 + lo) * 16 + 4 * hi) =
+                            u2v{h01, h23};
+                }
             }
-            // transposed: weights as the row operand, the patch fragment as
-            // the column operand (the same registers); the lane gets
-            // channels 4hi..4hi+3 of position (oy, lo), written as 8 bytes
-            f4 c = mfma(bw1, a, f4{0.f, 0.f, 0.f, 0.f});
-            const s4 h = pack4(fmaxf(c[0] + b1q[0], 0.f), fmaxf(c[1] + b1q[1], 0.f),
-                               fmaxf(c[2] + b1q[2], 0.f), fmaxf(c[3] + b1q[3], 0.f));
-            const int pos = oy * 16 + lo;
-            uint32_t *hw = reinterpret_cast<uint32_t *>(H1 + pos * kPosPitch + 4 * hi);
-            hw[0] = (uint32_t)(uint16_t)h.x | ((uint32_t)(uint16_t)h.y << 16);
-            hw[1] = (uint32_t)(uint16_t)h.z | ((uint32_t)(uint16_t)h.w << 16);
-            if (kTrain) {
-                uint16_t *hs = A.H1st + (pid * 256 + pos) * 16 + 4 * hi;
-                hs[0] = (uint16_t)h.x; hs[1] = (uint16_t)h.y;
-                hs[2] = (uint16_t)h.z; hs[3] = (uint16_t)h.w;
-            }
-        }
+        };
+        if (oc & 1)
+            conv1(std::true_type{});
+        else
+            conv1(std::false_type{});
         wave_lds_sync();
-        // ---- conv2: 49 output positions in 4 row tiles, 9 taps of 16 channels
+
+        // ---- conv2 (transposed): 49 output positions in 4 column tiles of
+        // 16, 9 taps of 16 channels in 5 x32 steps; the four tiles'
+        // accumulations interleaved (independent MFMA chains)
         {
-            // the four row tiles' accumulations interleaved (independent
-            // MFMA chains)
-            int ty[4], tx[4];
+            f4 c2[4] = {b2v, b2v, b2v, b2v};
 #pragma unroll
-            for (int t = 0; t < 4; t++) {
-                int m = 16 * t + lo;
-                m = m > 48 ? 48 : m;
-                ty[t] = m / 7;
-                tx[t] = m - ty[t] * 7;
-            }
-            f4 c[4] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f},
-                       {0.f, 0.f, 0.f, 0.f}};
-#pragma unroll
-            for (int tap = 0; tap < 9; tap++) {
-                const int ky = tap / 3, kx = tap - ky * 3;
+            for (int j = 0; j < 5; j++) {
 #pragma unroll
                 for (int t = 0; t < 4; t++) {
-                    // 4 consecutive channels of one input position
-                    const s4 a = lds_frag(H1 + ((2 * ty[t] + ky) * 16 + (2 * tx[t] + kx)) * kPosPitch + 4 * hi);
-                    c[t] = mfma(a, bw2[tap], c[t]);
+                    const s8 b = lds_frag8(H1 + base2[t] + toff2[j]);
+                    c2[t] = mfma32(aw2[j], b, c2[t]);
                 }
             }
 #pragma unroll
             for (int t = 0; t < 4; t++) {
-#pragma unroll
-                for (int i = 0; i < 4; i++) {
-                    const int pos = 16 * t + 4 * hi + i;
-                    if (pos < 49) {
-                        const uint16_t h = (uint16_t)bf16_bits(fmaxf(c[t][i] + b2, 0.f));
-                        H2[pos * kPosPitch + lo] = h;
-                        if (kTrain)
-                            A.H2st[(pid * 49 + pos) * 16 + lo] = h;
-                    }
-                }
+                const uint32_t h01 = relu_bf16x2(pk_bf16(c2[t][0], c2[t][1]));
+                const uint32_t h23 = relu_bf16x2(pk_bf16(c2[t][2], c2[t][3]));
+                *reinterpret_cast<u2v *>(H2 + w2off + t * 256) = u2v{h01, h23};
+                if (kTrain && 16 * t + lo < 49)
+                    *reinterpret_cast<u2v *>(A.H2st + (pid * 49 + 16 * t + lo) * 16 + 4 * hi) =
+                        u2v{h01, h23};
             }
         }
         wave_lds_sync();
         // ---- conv3: 9 output positions, 2 column tiles of 16 channels
-        f4 c3[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
-        {
-            int m = lo > 8 ? 8 : lo;
-            const int oy = m / 3, ox = m - oy * 3;
+        f4 c3[2] = {{b3[0], b3[0], b3[0], b3[0]}, {b3[1], b3[1], b3[1], b3[1]}};
 #pragma unroll
-            for (int tap = 0; tap < 9; tap++) {
-                const int ky = tap / 3, kx = tap - ky * 3;
-                const s4 a = lds_frag(H2 + ((2 * oy + ky) * 7 + (2 * ox + kx)) * kPosPitch + 4 * hi);
-                c3[0] = mfma(a, bw3[tap][0], c3[0]);
-                c3[1] = mfma(a, bw3[tap][1], c3[1]);
-            }
+        for (int j = 0; j < 5; j++) {
+            const s8 a = lds_frag8(H2 + off3[j]);
+            c3[0] = mfma32(a, bw3[j][0], c3[0]);
+            c3[1] = mfma32(a, bw3[j][1], c3[1]);
         }
         // ---- ReLU, global average pool over the 9 positions, FC: each
         // lane's share of the FC sum over its channels and positions, then
@@ -380,7 +448,7 @@ __global__ __launch_bounds__(64 * kFwdWaves) void cnn_fwd_kernel(FwdArgs A)
 #pragma unroll
             for (int i = 0; i < 4; i++) {
                 const int pos = 4 * hi + i;
-                const float h = fmaxf(c3[nt][i] + b3[nt], 0.f);
+                const float h = fmaxf(c3[nt][i], 0.f);
                 if (pos < 9) {
                     s += h;
                     if (kTrain)
@@ -757,7 +825,7 @@ extern "C" int siting_cnn_forward(const float *params, const int16_t *z, int64_t
     a.centres = centres; a.nposts = B;
     a.Pst = w.P; a.H1st = w.H1; a.H2st = w.H2; a.H3st = w.H3; a.gst = w.g; a.yst = w.y;
     hipStream_t s = as_stream(stream);
-    const size_t lds = kFwdWaves * (kWaveLdsElems * 2 + kPatch * kPatch * 2);
+    const size_t lds = kFwdWaves * (kWaveLdsBytes + kPatch * kPatch * 2);
     const int64_t grid = std::min<int64_t>((B + kFwdWaves - 1) / kFwdWaves,
                                            (int64_t)device_cus() * 8);
     hipLaunchKernelGGL(cnn_fwd_kernel<true>, dim3((unsigned)grid), dim3(64 * kFwdWaves), lds, s, a);
@@ -902,7 +970,7 @@ extern "C" int siting_cnn_score_terrain(const float *params, const int16_t *z, i
     a.blocks_c = (a.lat_c + a.BL - 1) / a.BL;
     a.score = score;
     const int tw = a.BL * stride + kPatch - 1;
-    const size_t lds = kFwdWaves * kWaveLdsElems * 2 + (size_t)tw * ((tw + 3) & ~3) * 2;
+    const size_t lds = kFwdWaves * kWaveLdsBytes + (size_t)tw * ((tw + 3) & ~3) * 2;
     if ((int64_t)lds > kernel_max_dynamic_lds(reinterpret_cast<const void *>(&cnn_fwd_kernel<false>))) {
         set_error("%s: tile does not fit in LDS", fn);
         return SITING_E_UNSUPPORTED;
