@@ -39,12 +39,36 @@ typedef uint32_t u4v __attribute__((ext_vector_type(4)));
 constexpr int OW1 = 0, OB1 = 256, OW2 = 272, OB2 = 2576, OW3 = 2592, OB3 = 7200, OWFC = 7232,
               OBFC = 7264, NPARAMS = 7265;
 constexpr int kPatch = 64;
-constexpr int kFwdWaves = 4;
+// wavefronts per workgroup: training stages a tile per wavefront; scoring
+// shares one tile among the workgroup's wavefronts (two workgroups per CU)
+constexpr int kTrainWaves = 4, kScoreWaves = 4;
+template <bool kTrain>
+constexpr int fwd_waves() { return kTrain ? kTrainWaves : kScoreWaves; }
 // per-wavefront LDS: conv1 and conv2 activations, 16-byte entries of 8
-// bf16 channels (two entries per position)
-constexpr int kH1Bytes = 2 * 256 * 16;
-constexpr int kH2Bytes = 2 * 64 * 16;
+// bf16 channels (two entries per position).  H1 rows are 20 entries (16
+// columns and 4 of padding): two rows apart is then 8 entries (128 bytes)
+// apart modulo 256, so the two rows that one 16-lane group of conv2 reads
+// fall in different banks.
+constexpr int kH1Row = 20;
+constexpr int kH1Rows = 16;
+constexpr int kH1Chunk = kH1Rows * kH1Row;
+constexpr int kH1Bytes = 2 * kH1Chunk * 16;
+// H2 keeps the 7 valid rows of conv2's 8 x 8 output grid
+constexpr int kH2Chunk = 7 * 8;
+constexpr int kH2Bytes = 2 * kH2Chunk * 16;
 constexpr int kWaveLdsBytes = kH1Bytes + kH2Bytes;
+// Terrain tile row pitch in posts: at least the width and 2 modulo 4, so
+// rows start 4-byte aligned and consecutive rows are an odd number of
+// dwords apart.  conv1's 32-lane half reads two consecutive rows, 16 lanes
+// each two dwords apart: the odd offset puts the two rows in opposite
+// banks.
+__host__ __device__ constexpr int tile_pitch(int w) { return w + ((2 - w) & 3); }
+constexpr int kTrainPitch = tile_pitch(kPatch);
+// Scoring tiles cover BL x BL cells with BL * stride <= 64, so a tile side
+// is at most 127 posts and the pitch is one constant (row offsets become
+// instruction immediates).
+constexpr int kScoreSpan = 64;
+constexpr int kScorePitch = tile_pitch(kScoreSpan + kPatch - 1);
 
 __device__ __forceinline__ short bf16_bits(float f)
 {
@@ -157,18 +181,20 @@ struct FwdArgs {
 };
 
 template <bool kTrain>
-__global__ __launch_bounds__(64 * kFwdWaves) __attribute__((amdgpu_waves_per_eu(2, 2))) void
+__global__ __launch_bounds__(64 * fwd_waves<kTrain>())
+__attribute__((amdgpu_waves_per_eu(2, 2))) void
 cnn_fwd_kernel(FwdArgs A)
 {
     extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int kFwdWaves = fwd_waves<kTrain>();
     const int lane = threadIdx.x & 63;
     // the wavefront index as a uniform value: per-post bookkeeping (cell,
     // highest post, patch origin) then stays in scalar registers
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lo = lane & 15, hi = lane >> 4;
     // per-wavefront activations in 16-byte entries of 8 channels:
-    //   H1 [chunk 2][row 16][column 16: even columns, then odd] (8 KB)
-    //   H2 [chunk 2][position 64] (2 KB; positions 49..63 unused)
+    //   H1 [chunk 2][row 16][column 16: even columns, then odd; 4 pad]
+    //   H2 [chunk 2][row 7][column 8] (column 7 unused)
     // chunk c holds channels 8c..8c+7.  An x32 fragment is one entry; the
     // 3x3 stride-2 conv2 reads input columns 2tx+kx, which this column
     // order makes consecutive in tx.
@@ -206,24 +232,27 @@ cnn_fwd_kernel(FwdArgs A)
     const float bfc = p[OBFC];
 
     // per-lane LDS byte offsets, the same for every post
-    // conv1 output: channels 4hi..4hi+3 of column lo (row oy adds oy * 256)
-    const uint32_t w1off = ((hi >> 1) * 256 + (lo & 1) * 8 + (lo >> 1)) * 16 + (hi & 1) * 8;
-    // conv2 input: position 16t+lo (clamped to 48) of row tile t, tap of x32 step j
+    // conv1 output: channels 4hi..4hi+3 of column lo (row oy adds
+    // oy * kH1Row entries)
+    const uint32_t w1off = ((hi >> 1) * kH1Chunk + (lo & 1) * 8 + (lo >> 1)) * 16 + (hi & 1) * 8;
+    // conv2 runs on an 8 x 8 output grid (row 7 and column 7 discarded):
+    // tile t is rows 2t, 2t+1, lane lo is row 2t + lo/8, column lo%8.
+    // Output row 7 reads the inputs of row 6 (it is discarded).
     uint32_t base2[4], toff2[5];
 #pragma unroll
     for (int t = 0; t < 4; t++) {
-        const int n = 16 * t + lo > 48 ? 48 : 16 * t + lo;
-        const int ty = n / 7, tx = n - ty * 7;
-        base2[t] = ((hi & 1) * 256 + 2 * ty * 16 + tx) * 16;
+        const int ty = 2 * t + (lo >> 3) > 6 ? 6 : 2 * t + (lo >> 3), tx = lo & 7;
+        base2[t] = ((hi & 1) * kH1Chunk + 2 * ty * kH1Row + tx) * 16;
     }
 #pragma unroll
     for (int j = 0; j < 5; j++) {
         const int tap = 2 * j + half > 8 ? 8 : 2 * j + half;
         const int ky = tap / 3, kx = tap - 3 * ky;
-        toff2[j] = (ky * 16 + (kx == 1 ? 8 : kx == 2 ? 1 : 0)) * 16;
+        toff2[j] = (ky * kH1Row + (kx == 1 ? 8 : kx == 2 ? 1 : 0)) * 16;
     }
-    // conv2 output: channels 4hi..4hi+3 of position 16t+lo (t adds t * 256)
-    const uint32_t w2off = ((hi >> 1) * 64 + lo) * 16 + (hi & 1) * 8;
+    // conv2 output: channels 4hi..4hi+3 of grid position 16t+lo (t adds
+    // 16 entries)
+    const uint32_t w2off = ((hi >> 1) * kH2Chunk + lo) * 16 + (hi & 1) * 8;
     // conv3 input: position min(lo, 8) of the 3 x 3 output, tap of step j
     uint32_t off3[5];
     {
@@ -233,59 +262,126 @@ cnn_fwd_kernel(FwdArgs A)
         for (int j = 0; j < 5; j++) {
             const int tap = 2 * j + half > 8 ? 8 : 2 * j + half;
             const int ky = tap / 3, kx = tap - 3 * ky;
-            off3[j] = ((hi & 1) * 64 + (2 * oy + ky) * 7 + 2 * ox + kx) * 16;
+            off3[j] = ((hi & 1) * kH2Chunk + (2 * oy + ky) * 8 + 2 * ox + kx) * 16;
         }
     }
 
     // tile geometry
     int tw = kPatch, th = kPatch;  // tile width/height in posts
-    int tp = kPatch;               // tile row pitch (a multiple of 4 posts)
+    constexpr int tp = kTrain ? kTrainPitch : kScorePitch;  // tile row pitch in posts
     int64_t ty0 = 0, tx0 = 0;      // global post of tile (0,0) (unclamped)
     int nloc = 1;                  // posts handled by this workgroup
     int64_t bi = 0, bj = 0;        // this workgroup's block of cells
+    bool narrow = false;           // the tile's elevation range is <= 32767
     if (!kTrain) {
         bi = blockIdx.x / A.blocks_c;
         bj = blockIdx.x - bi * A.blocks_c;
         // patches are centred on the highest post of each cell: up to
         // stride-1 posts past the cell corner
         tw = th = A.BL * A.stride + kPatch - 1;
-        tp = (tw + 3) & ~3;
         ty0 = bi * A.BL * A.stride - kPatch / 2;
         tx0 = bj * A.BL * A.stride - kPatch / 2;
         // stage the clamped tile once for the whole workgroup: rows by
-        // wavefronts, columns by lanes, four rows' loads in flight at once
-        for (int r0 = wave; r0 < th; r0 += 4 * kFwdWaves) {
-            int16_t v[4][4];
+        // wavefronts, columns by lanes, four rows' loads in flight at once.
+        // Interior tiles of an even-pitch terrain move dwords (two posts);
+        // others clamp post by post.  Both track the tile's elevation range.
+        const int ndw = (tw + 1) >> 1;
+        const bool dwords = ty0 >= 0 && tx0 >= 0 && ty0 + th <= A.nrows &&
+                            tx0 + 2 * ndw <= A.ncols && ((A.ld | tx0) & 1) == 0 &&
+                            (reinterpret_cast<uintptr_t>(A.z) & 3) == 0;
+        sh2 zmax = {-32768, -32768}, zmin = {32767, 32767};
+        if (dwords) {
+            const int16_t *zt = A.z + ty0 * A.ld + tx0;
+            for (int r0 = wave; r0 < th; r0 += 4 * kFwdWaves) {
+                uint32_t v[4][2];
 #pragma unroll
-            for (int u = 0; u < 4; u++) {
-                const int r = r0 + u * kFwdWaves;
-                int64_t gy = ty0 + r;
-                gy = gy < 0 ? 0 : gy > A.nrows - 1 ? A.nrows - 1 : gy;
-                const int16_t *src = A.z + gy * A.ld;
+                for (int u = 0; u < 4; u++) {
+                    const int r = r0 + u * kFwdWaves;
+                    const uint32_t *src =
+                        reinterpret_cast<const uint32_t *>(zt + (int64_t)(r < th ? r : th - 1) * A.ld);
 #pragma unroll
-                for (int cc = 0; cc < 4; cc++) {
-                    const int c = lane + 64 * cc;
-                    int64_t gx = tx0 + c;
-                    gx = gx < 0 ? 0 : gx > A.ncols - 1 ? A.ncols - 1 : gx;
-                    v[u][cc] = (r < th && c < tw) ? src[gx] : (int16_t)0;
+                    for (int cc = 0; cc < 2; cc++) {
+                        const int c2 = lane + 64 * cc;
+                        v[u][cc] = c2 < ndw ? src[c2] : 0u;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const int r = r0 + u * kFwdWaves;
+#pragma unroll
+                    for (int cc = 0; cc < 2; cc++) {
+                        const int c2 = lane + 64 * cc;
+                        if (r < th && c2 < ndw) {
+                            *reinterpret_cast<uint32_t *>(tile + r * tp + 2 * c2) = v[u][cc];
+                            const sh2 x = __builtin_bit_cast(sh2, v[u][cc]);
+                            zmax = __builtin_elementwise_max(zmax, x);
+                            zmin = __builtin_elementwise_min(zmin, x);
+                        }
+                    }
                 }
             }
+        } else {
+            for (int r0 = wave; r0 < th; r0 += 4 * kFwdWaves) {
+                int16_t v[4][4];
 #pragma unroll
-            for (int u = 0; u < 4; u++) {
-                const int r = r0 + u * kFwdWaves;
+                for (int u = 0; u < 4; u++) {
+                    const int r = r0 + u * kFwdWaves;
+                    int64_t gy = ty0 + r;
+                    gy = gy < 0 ? 0 : gy > A.nrows - 1 ? A.nrows - 1 : gy;
+                    const int16_t *src = A.z + gy * A.ld;
 #pragma unroll
-                for (int cc = 0; cc < 4; cc++) {
-                    const int c = lane + 64 * cc;
-                    if (r < th && c < tw)
-                        tile[r * tp + c] = v[u][cc];
+                    for (int cc = 0; cc < 4; cc++) {
+                        const int c = lane + 64 * cc;
+                        int64_t gx = tx0 + c;
+                        gx = gx < 0 ? 0 : gx > A.ncols - 1 ? A.ncols - 1 : gx;
+                        v[u][cc] = (r < th && c < tw) ? src[gx] : (int16_t)0;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const int r = r0 + u * kFwdWaves;
+#pragma unroll
+                    for (int cc = 0; cc < 4; cc++) {
+                        const int c = lane + 64 * cc;
+                        if (r < th && c < tw) {
+                            tile[r * tp + c] = v[u][cc];
+                            const sh2 x = {v[u][cc], v[u][cc]};
+                            zmax = __builtin_elementwise_max(zmax, x);
+                            zmin = __builtin_elementwise_min(zmin, x);
+                        }
+                    }
                 }
             }
         }
+        // workgroup range: per-wave maxima of z + 32768 and 32767 - z in
+        // four slots past the tile
+        uint32_t *slots = reinterpret_cast<uint32_t *>(tile + th * tp);
+        const int lmax = zmax.x > zmax.y ? zmax.x : zmax.y, lmin = zmin.x < zmin.y ? zmin.x : zmin.y;
+        const uint32_t wmax = wave_max_u32((uint32_t)(lmax + 32768));
+        const uint32_t wmin = wave_max_u32((uint32_t)(32767 - lmin));
+        if (lane == 0) {
+            slots[2 * wave] = wmax;
+            slots[2 * wave + 1] = wmin;
+        }
         __syncthreads();
+        uint32_t gmax = 0, gmin = 0;
+#pragma unroll
+        for (int k = 0; k < kFwdWaves; k++) {
+            gmax = slots[2 * k] > gmax ? slots[2 * k] : gmax;
+            gmin = slots[2 * k + 1] > gmin ? slots[2 * k + 1] : gmin;
+        }
+        // every difference to a centre fits 16 bits
+        narrow = (int)gmax + (int)gmin - 65535 <= 32767;
         nloc = A.BL * A.BL;
     } else {
-        tile += wave * kPatch * kPatch;
+        tile += wave * kPatch * kTrainPitch;
     }
+
+    // the post a lane tests in the highest-post search of a cell of at most
+    // 64 posts
+    const int e1 = !kTrain && lane < A.stride * A.stride ? lane : 0;
+    const int hr = kTrain ? 0 : e1 / A.stride, hc = kTrain ? 0 : e1 - hr * A.stride;
+    const int hoff = hr * tp + hc;
 
     const int64_t nwork = kTrain ? A.nposts : nloc;
     const int64_t step = kTrain ? (int64_t)gridDim.x * kFwdWaves : kFwdWaves;
@@ -304,7 +400,7 @@ cnn_fwd_kernel(FwdArgs A)
                 int64_t gy = cy - kPatch / 2 + r, gx = cx - kPatch / 2 + lane;
                 gy = gy < 0 ? 0 : gy > A.nrows - 1 ? A.nrows - 1 : gy;
                 gx = gx < 0 ? 0 : gx > A.ncols - 1 ? A.ncols - 1 : gx;
-                tile[r * kPatch + lane] = A.z[gy * A.ld + gx];
+                tile[r * kTrainPitch + lane] = A.z[gy * A.ld + gx];
             }
             wave_lds_sync();
         } else {
@@ -317,14 +413,21 @@ cnn_fwd_kernel(FwdArgs A)
             // highest post of the cell (elevation desc, index asc): one wave
             // max over packed (elevation, ~row-major position) keys
             const int ss = A.stride * A.stride;
+            const int cell0 = (py * A.stride + kPatch / 2) * tp + px * A.stride + kPatch / 2;
             int best = -1;
-            for (int e = lane; e < ss; e += 64) {
-                const int r = e / A.stride, c = e - r * A.stride;
-                if (li * A.stride + r < A.nrows && lj * A.stride + c < A.ncols) {
-                    const int v = tile[(py * A.stride + r + kPatch / 2) * tp +
-                                       px * A.stride + c + kPatch / 2];
-                    const int key = ((v + 32768) << 12) | (4095 - e);
-                    best = key > best ? key : best;
+            if (ss <= 64) {
+                // one post per lane (row hr, column hc of the cell)
+                const bool ok = lane < ss && li * A.stride + hr < A.nrows && lj * A.stride + hc < A.ncols;
+                const int v = tile[cell0 + hoff];
+                best = ok ? ((v + 32768) << 12) | (4095 - e1) : -1;
+            } else {
+                for (int e = lane; e < ss; e += 64) {
+                    const int r = e / A.stride, c = e - r * A.stride;
+                    if (li * A.stride + r < A.nrows && lj * A.stride + c < A.ncols) {
+                        const int v = tile[cell0 + r * tp + c];
+                        const int key = ((v + 32768) << 12) | (4095 - e);
+                        best = key > best ? key : best;
+                    }
                 }
             }
             // every key is positive (the cell has a post), so the zeros the
@@ -341,17 +444,24 @@ cnn_fwd_kernel(FwdArgs A)
 
         // ---- conv1: one MFMA per output row oy (16 output columns).  The
         // four posts of a fragment are two dwords: rows start dword-aligned
-        // (tp is a multiple of 4), so they are aligned when oc is even and
-        // otherwise take three dwords shifted by one post.
-        // All 16 rows are read before the first H1 write, so that the
-        // compiler may overlap one row's conversion with another's MFMA
-        // (the LDS writes would otherwise order every later read).
-        auto conv1 = [&](auto odd) {
+        // (tp is even), so they are aligned when oc is even and otherwise
+        // take three dwords shifted by one post.  All rows are read before
+        // the first H1 write, so that the compiler may overlap one row's
+        // conversion with another's MFMA (the LDS writes would otherwise
+        // order every later read).  With a narrow tile the differences are
+        // formed as packed 16-bit integers (exact there) and converted from
+        // 16 bits, the same values as the 32-bit path.  Row 15 feeds no
+        // conv2 output: scoring skips it, training computes it for the
+        // stored activations.
+        const uint32_t zc2 = (uint32_t)(uint16_t)zc * 0x10001u;
+        auto conv1 = [&](auto odd, auto nar) {
             constexpr bool kOdd = decltype(odd)::value;
+            constexpr bool kNarrow = decltype(nar)::value;
+            constexpr int NR = kTrain ? 16 : 15;
             const int16_t *src0 = tile + (or_ + hi) * tp + oc + 4 * lo;
-            uint32_t P01[16], P23[16];
+            uint32_t P01[NR], P23[NR];
 #pragma unroll
-            for (int oy = 0; oy < 16; oy++) {
+            for (int oy = 0; oy < NR; oy++) {
                 const int16_t *src = src0 + 4 * oy * tp;
                 if (!kOdd) {
                     const uint32_t *q = reinterpret_cast<const uint32_t *>(src);
@@ -366,19 +476,29 @@ cnn_fwd_kernel(FwdArgs A)
             }
             // four rows at a time: four independent MFMAs in flight
 #pragma unroll
-            for (int g = 0; g < 16; g += 4) {
+            for (int g = 0; g < NR; g += 4) {
                 f4 c[4];
 #pragma unroll
-                for (int u = 0; u < 4; u++) {
+                for (int u = 0; u < 4 && g + u < NR; u++) {
                     const int oy = g + u;
                     const uint32_t p01 = P01[oy], p23 = P23[oy];
                     // elevation differences in units of 256 m (exact
                     // power-of-two scale)
                     constexpr float kScale = kTrain ? 0.00390625f : 1.0f;
-                    const float v0 = (float)((int)(int16_t)(p01 & 0xFFFFu) - zc) * kScale;
-                    const float v1 = (float)((int)(int16_t)(p01 >> 16) - zc) * kScale;
-                    const float v2 = (float)((int)(int16_t)(p23 & 0xFFFFu) - zc) * kScale;
-                    const float v3 = (float)((int)(int16_t)(p23 >> 16) - zc) * kScale;
+                    float v0, v1, v2, v3;
+                    if (kNarrow) {
+                        const sh2 d01 = __builtin_bit_cast(sh2, p01) - __builtin_bit_cast(sh2, zc2);
+                        const sh2 d23 = __builtin_bit_cast(sh2, p23) - __builtin_bit_cast(sh2, zc2);
+                        v0 = (float)d01.x * kScale;
+                        v1 = (float)d01.y * kScale;
+                        v2 = (float)d23.x * kScale;
+                        v3 = (float)d23.y * kScale;
+                    } else {
+                        v0 = (float)((int)(int16_t)(p01 & 0xFFFFu) - zc) * kScale;
+                        v1 = (float)((int)(int16_t)(p01 >> 16) - zc) * kScale;
+                        v2 = (float)((int)(int16_t)(p23 & 0xFFFFu) - zc) * kScale;
+                        v3 = (float)((int)(int16_t)(p23 >> 16) - zc) * kScale;
+                    }
                     const uint64_t a = (uint64_t)pk_bf16(v0, v1) | ((uint64_t)pk_bf16(v2, v3) << 32);
                     if (kTrain)
                         *reinterpret_cast<uint64_t *>(A.Pst + pid * 4096 + (4 * oy + hi) * 64 + 4 * lo) = a;
@@ -387,26 +507,33 @@ cnn_fwd_kernel(FwdArgs A)
                     c[u] = mfma(bw1, __builtin_bit_cast(s4, a), b1v);
                 }
 #pragma unroll
-                for (int u = 0; u < 4; u++) {
+                for (int u = 0; u < 4 && g + u < NR; u++) {
                     const int oy = g + u;
                     // ReLU on the rounded bf16 pairs
                     const uint32_t h01 = relu_bf16x2(pk_bf16(c[u][0], c[u][1]));
                     const uint32_t h23 = relu_bf16x2(pk_bf16(c[u][2], c[u][3]));
-                    *reinterpret_cast<u2v *>(H1 + w1off + oy * 256) = u2v{h01, h23};
+                    *reinterpret_cast<u2v *>(H1 + w1off + oy * kH1Row * 16) = u2v{h01, h23};
                     if (kTrain)
                         *reinterpret_cast<u2v *>(A.H1st + (pid * 256 + oy * 16 + lo) * 16 + 4 * hi) =
                             u2v{h01, h23};
                 }
             }
         };
-        if (oc & 1)
-            conv1(std::true_type{});
-        else
-            conv1(std::false_type{});
+        if (narrow) {
+            if (oc & 1)
+                conv1(std::true_type{}, std::true_type{});
+            else
+                conv1(std::false_type{}, std::true_type{});
+        } else {
+            if (oc & 1)
+                conv1(std::true_type{}, std::false_type{});
+            else
+                conv1(std::false_type{}, std::false_type{});
+        }
         wave_lds_sync();
 
-        // ---- conv2 (transposed): 49 output positions in 4 column tiles of
-        // 16, 9 taps of 16 channels in 5 x32 steps; the four tiles'
+        // ---- conv2 (transposed): the 7 x 7 outputs in 4 tiles of 16 grid
+        // positions, 9 taps of 16 channels in 5 x32 steps; the four tiles'
         // accumulations interleaved (independent MFMA chains)
         {
             f4 c2[4] = {b2v, b2v, b2v, b2v};
@@ -422,9 +549,11 @@ cnn_fwd_kernel(FwdArgs A)
             for (int t = 0; t < 4; t++) {
                 const uint32_t h01 = relu_bf16x2(pk_bf16(c2[t][0], c2[t][1]));
                 const uint32_t h23 = relu_bf16x2(pk_bf16(c2[t][2], c2[t][3]));
-                *reinterpret_cast<u2v *>(H2 + w2off + t * 256) = u2v{h01, h23};
-                if (kTrain && 16 * t + lo < 49)
-                    *reinterpret_cast<u2v *>(A.H2st + (pid * 49 + 16 * t + lo) * 16 + 4 * hi) =
+                const int ty = 2 * t + (lo >> 3), tx = lo & 7;
+                if (ty < 7)
+                    *reinterpret_cast<u2v *>(H2 + w2off + t * 256) = u2v{h01, h23};
+                if (kTrain && ty < 7 && tx < 7)
+                    *reinterpret_cast<u2v *>(A.H2st + (pid * 49 + ty * 7 + tx) * 16 + 4 * hi) =
                         u2v{h01, h23};
             }
         }
@@ -448,22 +577,25 @@ cnn_fwd_kernel(FwdArgs A)
 #pragma unroll
             for (int i = 0; i < 4; i++) {
                 const int pos = 4 * hi + i;
-                const float h = fmaxf(c3[nt][i], 0.f);
+                // ReLU as an integer maximum of the bits (negative floats
+                // are negative integers)
+                const float h = __int_as_float(max(__float_as_int(c3[nt][i]), 0));
                 if (pos < 9) {
                     s += h;
                     if (kTrain)
                         A.H3st[(pid * 9 + pos) * 32 + nt * 16 + lo] = h;
                 }
             }
-            part += wfc[nt] * (s / 9.0f);
+            part += wfc[nt] * s;
             if (kTrain) {
                 float gs = s + __shfl_xor(s, 16, 64);
                 gs += __shfl_xor(gs, 32, 64);
                 if (hi == 0)
-                    A.gst[pid * 32 + nt * 16 + lo] = gs / 9.0f;
+                    A.gst[pid * 32 + nt * 16 + lo] = gs * (1.0f / 9.0f);
             }
         }
-        const float y = wave_sum_f32(part) + bfc;
+        // the pool's 1/9 applied once to the sum
+        const float y = wave_sum_f32(part) * (1.0f / 9.0f) + bfc;
         if (lane == 0) {
             if (kTrain)
                 A.yst[pid] = y;
@@ -825,10 +957,10 @@ extern "C" int siting_cnn_forward(const float *params, const int16_t *z, int64_t
     a.centres = centres; a.nposts = B;
     a.Pst = w.P; a.H1st = w.H1; a.H2st = w.H2; a.H3st = w.H3; a.gst = w.g; a.yst = w.y;
     hipStream_t s = as_stream(stream);
-    const size_t lds = kFwdWaves * (kWaveLdsBytes + kPatch * kPatch * 2);
-    const int64_t grid = std::min<int64_t>((B + kFwdWaves - 1) / kFwdWaves,
+    const size_t lds = kTrainWaves * (kWaveLdsBytes + kPatch * kTrainPitch * 2);
+    const int64_t grid = std::min<int64_t>((B + kTrainWaves - 1) / kTrainWaves,
                                            (int64_t)device_cus() * 8);
-    hipLaunchKernelGGL(cnn_fwd_kernel<true>, dim3((unsigned)grid), dim3(64 * kFwdWaves), lds, s, a);
+    hipLaunchKernelGGL(cnn_fwd_kernel<true>, dim3((unsigned)grid), dim3(64 * kTrainWaves), lds, s, a);
     rc = check_launch("cnn_fwd_kernel");
     if (rc != SITING_OK || !pred)
         return rc;
@@ -963,14 +1095,16 @@ extern "C" int siting_cnn_score_terrain(const float *params, const int16_t *z, i
     FwdArgs a{};
     a.params = params; a.z = z; a.nrows = nrows; a.ncols = ncols; a.ld = ld;
     a.stride = stride;
-    a.BL = stride <= 8 ? 8 : (stride <= 24 ? 4 : 2);
+    // cells per tile side: BL * stride <= 64 posts plus the 63-post patch
+    // margin (two workgroups per CU at every stride)
+    a.BL = std::max(1, kScoreSpan / stride);
     a.lat_r = (nrows + stride - 1) / stride;
     a.lat_c = (ncols + stride - 1) / stride;
     const int64_t blocks_r = (a.lat_r + a.BL - 1) / a.BL;
     a.blocks_c = (a.lat_c + a.BL - 1) / a.BL;
     a.score = score;
     const int tw = a.BL * stride + kPatch - 1;
-    const size_t lds = kFwdWaves * kWaveLdsBytes + (size_t)tw * ((tw + 3) & ~3) * 2;
+    const size_t lds = kScoreWaves * kWaveLdsBytes + (size_t)tw * kScorePitch * 2 + 8 * kScoreWaves;
     if ((int64_t)lds > kernel_max_dynamic_lds(reinterpret_cast<const void *>(&cnn_fwd_kernel<false>))) {
         set_error("%s: tile does not fit in LDS", fn);
         return SITING_E_UNSUPPORTED;
@@ -980,7 +1114,7 @@ extern "C" int siting_cnn_score_terrain(const float *params, const int16_t *z, i
         set_error("%s: terrain too large", fn);
         return SITING_E_UNSUPPORTED;
     }
-    hipLaunchKernelGGL(cnn_fwd_kernel<false>, dim3((unsigned)grid), dim3(64 * kFwdWaves), lds,
+    hipLaunchKernelGGL(cnn_fwd_kernel<false>, dim3((unsigned)grid), dim3(64 * kScoreWaves), lds,
                        as_stream(stream), a);
     return check_launch("cnn_fwd_kernel");
 }
