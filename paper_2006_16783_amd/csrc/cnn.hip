@@ -174,7 +174,7 @@ struct FwdArgs {
     int64_t nposts;
     uint16_t *Pst, *H1st, *H2st;
     float *H3st, *gst, *yst;
-    // score mode
+    // score mode: tiles of BL x BL cells, one per workgroup, row-major
     int stride, BL;
     int64_t lat_r, lat_c, blocks_c;
     float *score;
@@ -266,9 +266,15 @@ cnn_fwd_kernel(FwdArgs A)
         }
     }
 
+    // the post a lane tests in the highest-post search of a cell of at most
+    // 64 posts
+    constexpr int tp = kTrain ? kTrainPitch : kScorePitch;  // tile row pitch in posts
+    const int e1 = !kTrain && lane < A.stride * A.stride ? lane : 0;
+    const int hr = kTrain ? 0 : e1 / A.stride, hc = kTrain ? 0 : e1 - hr * A.stride;
+    const int hoff = hr * tp + hc;
+
     // tile geometry
     int tw = kPatch, th = kPatch;  // tile width/height in posts
-    constexpr int tp = kTrain ? kTrainPitch : kScorePitch;  // tile row pitch in posts
     int64_t ty0 = 0, tx0 = 0;      // global post of tile (0,0) (unclamped)
     int nloc = 1;                  // posts handled by this workgroup
     int64_t bi = 0, bj = 0;        // this workgroup's block of cells
@@ -282,47 +288,43 @@ cnn_fwd_kernel(FwdArgs A)
         ty0 = bi * A.BL * A.stride - kPatch / 2;
         tx0 = bj * A.BL * A.stride - kPatch / 2;
         // stage the clamped tile once for the whole workgroup: rows by
-        // wavefronts, columns by lanes, four rows' loads in flight at once.
-        // Interior tiles of an even-pitch terrain move dwords (two posts);
-        // others clamp post by post.  Both track the tile's elevation range.
+        // wavefronts, columns by lanes, several rows' loads in flight at
+        // once.  Interior tiles of an even-pitch terrain move dwords (two
+        // posts); others clamp post by post.  Both track the tile's
+        // elevation range.
         const int ndw = (tw + 1) >> 1;
         const bool dwords = ty0 >= 0 && tx0 >= 0 && ty0 + th <= A.nrows &&
                             tx0 + 2 * ndw <= A.ncols && ((A.ld | tx0) & 1) == 0 &&
                             (reinterpret_cast<uintptr_t>(A.z) & 3) == 0;
         sh2 zmax = {-32768, -32768}, zmin = {32767, 32767};
         if (dwords) {
-            const int16_t *zt = A.z + ty0 * A.ld + tx0;
-            for (int r0 = wave; r0 < th; r0 += 4 * kFwdWaves) {
-                uint32_t v[4][2];
+            // lane = dword column; this wavefront's rows are kFwdWaves apart
+            const bool lv = lane < ndw;
+            const int64_t rstep = (int64_t)kFwdWaves * (A.ld >> 1);
+            const uint32_t *zrow =
+                reinterpret_cast<const uint32_t *>(A.z + (ty0 + wave) * A.ld + tx0) + lane;
+            for (int r0 = wave; r0 < th; r0 += 8 * kFwdWaves) {
+                uint32_t v[8];
 #pragma unroll
-                for (int u = 0; u < 4; u++) {
+                for (int u = 0; u < 8; u++) {
                     const int r = r0 + u * kFwdWaves;
-                    const uint32_t *src =
-                        reinterpret_cast<const uint32_t *>(zt + (int64_t)(r < th ? r : th - 1) * A.ld);
-#pragma unroll
-                    for (int cc = 0; cc < 2; cc++) {
-                        const int c2 = lane + 64 * cc;
-                        v[u][cc] = c2 < ndw ? src[c2] : 0u;
-                    }
+                    v[u] = (r < th && lv) ? zrow[u * rstep] : 0u;
                 }
 #pragma unroll
-                for (int u = 0; u < 4; u++) {
+                for (int u = 0; u < 8; u++) {
                     const int r = r0 + u * kFwdWaves;
-#pragma unroll
-                    for (int cc = 0; cc < 2; cc++) {
-                        const int c2 = lane + 64 * cc;
-                        if (r < th && c2 < ndw) {
-                            *reinterpret_cast<uint32_t *>(tile + r * tp + 2 * c2) = v[u][cc];
-                            const sh2 x = __builtin_bit_cast(sh2, v[u][cc]);
-                            zmax = __builtin_elementwise_max(zmax, x);
-                            zmin = __builtin_elementwise_min(zmin, x);
-                        }
+                    if (r < th && lv) {
+                        *reinterpret_cast<uint32_t *>(tile + r * tp + 2 * lane) = v[u];
+                        const sh2 x = __builtin_bit_cast(sh2, v[u]);
+                        zmax = __builtin_elementwise_max(zmax, x);
+                        zmin = __builtin_elementwise_min(zmin, x);
                     }
                 }
+                zrow += 8 * rstep;
             }
         } else {
             for (int r0 = wave; r0 < th; r0 += 4 * kFwdWaves) {
-                int16_t v[4][4];
+                int16_t v[4][2];
 #pragma unroll
                 for (int u = 0; u < 4; u++) {
                     const int r = r0 + u * kFwdWaves;
@@ -330,7 +332,7 @@ cnn_fwd_kernel(FwdArgs A)
                     gy = gy < 0 ? 0 : gy > A.nrows - 1 ? A.nrows - 1 : gy;
                     const int16_t *src = A.z + gy * A.ld;
 #pragma unroll
-                    for (int cc = 0; cc < 4; cc++) {
+                    for (int cc = 0; cc < 2; cc++) {
                         const int c = lane + 64 * cc;
                         int64_t gx = tx0 + c;
                         gx = gx < 0 ? 0 : gx > A.ncols - 1 ? A.ncols - 1 : gx;
@@ -341,7 +343,7 @@ cnn_fwd_kernel(FwdArgs A)
                 for (int u = 0; u < 4; u++) {
                     const int r = r0 + u * kFwdWaves;
 #pragma unroll
-                    for (int cc = 0; cc < 4; cc++) {
+                    for (int cc = 0; cc < 2; cc++) {
                         const int c = lane + 64 * cc;
                         if (r < th && c < tw) {
                             tile[r * tp + c] = v[u][cc];
@@ -376,12 +378,6 @@ cnn_fwd_kernel(FwdArgs A)
     } else {
         tile += wave * kPatch * kTrainPitch;
     }
-
-    // the post a lane tests in the highest-post search of a cell of at most
-    // 64 posts
-    const int e1 = !kTrain && lane < A.stride * A.stride ? lane : 0;
-    const int hr = kTrain ? 0 : e1 / A.stride, hc = kTrain ? 0 : e1 - hr * A.stride;
-    const int hoff = hr * tp + hc;
 
     const int64_t nwork = kTrain ? A.nposts : nloc;
     const int64_t step = kTrain ? (int64_t)gridDim.x * kFwdWaves : kFwdWaves;

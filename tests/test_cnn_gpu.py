@@ -73,6 +73,37 @@ def test_score_equals_forward_at_cell_maxima(S):
         assert np.abs(pred - want).max() < 2e-3
 
 
+@pytest.mark.parametrize("n,ncols,stride,zlo,zhi", [
+    (1600, 1600, 8, 0, 3000),      # dword staging, two tiles per workgroup
+    (1040, 1040, 4, 0, 3000),      # 16 x 16 cells per tile
+    (300, 256, 8, -30000, 30000),  # elevation range above 32767
+    (300, 256, 5, -30000, 30000),
+])
+def test_score_paths_equal_forward(S, n, ncols, stride, zlo, zhi):
+    """Scoring's tile staging (dword moves on interior tiles of an even-pitch
+    terrain, post by post at the edges), its 16-bit differences (tiles whose
+    elevation range fits 16 bits) and its runs of tiles per workgroup give the
+    training forward's bits at every cell maximum; a sample against the
+    oracle where the range is realistic."""
+    from oracle import cnn
+    from synth import fbm
+    import oracle
+    z = fbm(n, 2.2, 3000, 11, ncols=ncols).astype(np.int64)
+    z = (zlo + (z - z.min()) * (zhi - zlo) // max(1, int(z.max() - z.min()))).astype(np.int16)
+    theta = cnn.init_params(5).astype(np.float32)
+    sc = S.siting_cnn_score_terrain(_dev(theta), _dev(z), stride).cpu().numpy().ravel()
+    centres = oracle.cell_max(z, stride)
+    ws = S.cnn_workspace(len(centres))
+    pred = S.siting_cnn_forward(_dev(theta), _dev(z), _dev(centres), ws).cpu().numpy()
+    del ws
+    assert (pred == sc).all(), int((pred != sc).sum())
+    if zhi - zlo <= 3000:
+        pick = np.random.default_rng(n).choice(len(centres), 48, replace=False)
+        P = cnn.patches(z, centres[pick], round=True)
+        want = cnn.forward(theta.astype(np.float64), P, round=True)["p"]
+        assert np.abs(sc[pick] - want).max() < 2e-3
+
+
 def test_backward_matches_oracle(S):
     from oracle import cnn
     z, centres, theta, labels = _case(2, 200)
