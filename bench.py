@@ -36,7 +36,7 @@ if ROOT not in sys.path:
 PEAK_HBM_GBS = 8000.0
 # 32-bit integer VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (non-packed)
 PEAK_INT_TOPS = 256 * 64 * 2.4e9 / 1e12
-# integer ALU operations of one line-of-sight step (see DESIGN.md): advance
+# integer ALU operations of one line-of-sight step: advance
 # the crossing (add, compare, conditional subtract), two address updates,
 # interpolate (subtract, two multiplies, add), advance the segment (add),
 # compare
@@ -44,6 +44,13 @@ VIX_OPS_PER_LOS_STEP = 11
 # one viewshed ray step: the line-of-sight step work plus the nearest-cell
 # rounding, disk test, horizon slope products and comparisons, bit address
 VIEWSHED_OPS_PER_RAY_STEP = 24
+# dense bf16 MFMA peak (TFLOP/s) and the ranking CNN's multiply-adds per
+# scored cell: conv1 16x16 positions x 16 channels x 16, conv2 7x7 x 16 x 144,
+# conv3 3x3 x 32 x 144, FC 32 (212,000 of them reach the output: conv1's
+# last row and column feed no conv2 output)
+PEAK_BF16_TFLOPS = 2500.0
+CNN_MACS_PER_CELL = 16 * 16 * 16 * 16 + 49 * 16 * 144 + 9 * 32 * 144 + 32
+CNN_MACS_TO_OUTPUT = 15 * 15 * 16 * 16 + 49 * 16 * 144 + 9 * 32 * 144 + 32
 
 
 def log(*a):
@@ -402,6 +409,18 @@ def main():
                "coverage_diff_pp": 100.0 * (sres.coverage_cells - last.coverage_cells) / (nr * nc),
                "speedup_vs_plain": ms_per_step / sur_ms,
                "weights": "paper_2006_16783_amd/weights/surrogate_r100_h10.npy"}
+        # the scoring kernel against the bf16 MFMA roof
+        st = args.surrogate_stride
+        cells = ((nr + st - 1) // st) * ((nc + st - 1) // st)
+        score_s = sur["stage_ms"]["score"] / 1e3
+        ach = cells * 2 * CNN_MACS_PER_CELL / score_s / 1e12
+        sur["cnn_roofline"] = {
+            "bound": "mfma", "kernel": "cnn_fwd_kernel", "achieved": ach,
+            "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s", "frac": ach / PEAK_BF16_TFLOPS,
+            "frac_output_macs": ach * CNN_MACS_TO_OUTPUT / CNN_MACS_PER_CELL / PEAK_BF16_TFLOPS,
+            "units_per_launch": {"cells": cells, "macs_per_cell": CNN_MACS_PER_CELL,
+                                 "macs_to_output_per_cell": CNN_MACS_TO_OUTPUT},
+            "kernel_ms": sur["stage_ms"]["score"]}
 
     cpu = None
     parity = None

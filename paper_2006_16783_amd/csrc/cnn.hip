@@ -147,6 +147,13 @@ __device__ __forceinline__ float wave_sum_f32(float v)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
+// logistic function; the hardware reciprocal (1 ulp) in place of a
+// correctly rounded division (every caller uses this one definition)
+__device__ __forceinline__ float sigmoid_f32(float y)
+{
+    return __builtin_amdgcn_rcpf(1.0f + __expf(-y));
+}
+
 __device__ __forceinline__ f4 mfma(s4 a, s4 b, f4 c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
@@ -413,7 +420,10 @@ cnn_fwd_kernel(FwdArgs A)
             int best = -1;
             if (ss <= 64) {
                 // one post per lane (row hr, column hc of the cell)
-                const bool ok = lane < ss && li * A.stride + hr < A.nrows && lj * A.stride + hc < A.ncols;
+                // rows and columns of the cell inside the terrain (uniform)
+                const int64_t rl64 = A.nrows - li * A.stride, cl64 = A.ncols - lj * A.stride;
+                const int rl = rl64 < 64 ? (int)rl64 : 64, cl = cl64 < 64 ? (int)cl64 : 64;
+                const bool ok = lane < ss && hr < rl && hc < cl;
                 const int v = tile[cell0 + hoff];
                 best = ok ? ((v + 32768) << 12) | (4095 - e1) : -1;
             } else {
@@ -596,7 +606,7 @@ cnn_fwd_kernel(FwdArgs A)
             if (kTrain)
                 A.yst[pid] = y;
             else
-                A.score[pid] = 1.0f / (1.0f + __expf(-y));
+                A.score[pid] = sigmoid_f32(y);
         }
         wave_lds_sync();
     }
@@ -613,7 +623,7 @@ __global__ void cnn_head_bwd(const float *__restrict__ params, const float *__re
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= B)
         return;
-    const float pr = 1.0f / (1.0f + __expf(-y[b]));
+    const float pr = sigmoid_f32(y[b]);
     const float e = pr - labels[b];
     const float d = 2.0f * e / (float)B * pr * (1.0f - pr);
     dy[b] = d;
@@ -834,7 +844,7 @@ __global__ void sigmoid_kernel(const float *__restrict__ y, int64_t n, float *__
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n)
-        p[i] = 1.0f / (1.0f + __expf(-y[i]));
+        p[i] = sigmoid_f32(y[i]);
 }
 
 __global__ void to_bf16(const float *__restrict__ x, int64_t n, uint16_t *__restrict__ y)
