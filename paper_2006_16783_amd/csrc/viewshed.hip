@@ -486,16 +486,22 @@ __device__ __forceinline__ int isqrt_floor(int v)
     return s;
 }
 
+// One instantiation per mode and ray schedule, so that the common path (mode
+// 0, a lane per ray) carries neither the other modes' code nor the
+// wavefront-per-ray sweep's registers.
+template <int kMode, bool kRayWave>
 __global__ void viewshed_kernel(const int16_t *__restrict__ z, int64_t nrows, int64_t ncols,
                                 int64_t ld, const siting_observer *__restrict__ obs, int64_t n,
                                 const int64_t *__restrict__ offsets,
                                 const int32_t *__restrict__ order, int sink,
                                 uint64_t *__restrict__ bitmaps, uint32_t *__restrict__ visible,
                                 uint32_t *__restrict__ cells, uint32_t *queue, int rmax,
-                                int stage_rmax, int dma, int mode, int ray_wave)
+                                int stage_rmax, int dma)
 {
     // mode 0: window bitmap in LDS; 1: quadrant mode; 2: global-bitmap mode
-    const int quad = mode == 1;
+    constexpr int mode = kMode;
+    constexpr bool ray_wave = kRayWave;
+    constexpr bool quad = mode == 1;
     extern __shared__ uint32_t lds[];
     __shared__ int64_t s_task;
     __shared__ int s_red[2 * 16];
@@ -945,7 +951,7 @@ __global__ void viewshed_kernel(const int16_t *__restrict__ z, int64_t nrows, in
 
 int viewshed_max_dynamic_lds()
 {
-    return kernel_max_dynamic_lds(reinterpret_cast<const void *>(&viewshed_kernel));
+    return kernel_max_dynamic_lds(reinterpret_cast<const void *>(&viewshed_kernel<0, false>));
 }
 
 // Windows whose bitmap exceeds LDS run in quadrant mode (terrain from global
@@ -1001,9 +1007,14 @@ int viewshed_launch(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld,
         return SITING_OK;
     // direct HBM-to-LDS staging needs dword-aligned rows that hold whole dwords
     const int dma = ld % 2 == 0 && ncols % 2 == 0 && reinterpret_cast<uintptr_t>(z) % 4 == 0;
-    hipLaunchKernelGGL(viewshed_kernel, dim3((unsigned)grid), dim3(64 * sc.waves), (size_t)lds, s,
-                       z, nrows, ncols, ld, obs, n, offsets, order, sink, bitmaps, visible, cells,
-                       queue, rmax, stage, dma, mode, sc.ray_per_wave);
+    const bool rw = sc.ray_per_wave != 0;
+    decltype(&viewshed_kernel<0, false>) k =
+        mode == 0 ? (rw ? viewshed_kernel<0, true> : viewshed_kernel<0, false>)
+        : mode == 1 ? (rw ? viewshed_kernel<1, true> : viewshed_kernel<1, false>)
+                    : (rw ? viewshed_kernel<2, true> : viewshed_kernel<2, false>);
+    hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(64 * sc.waves), (size_t)lds, s, z, nrows,
+                       ncols, ld, obs, n, offsets, order, sink, bitmaps, visible, cells, queue,
+                       rmax, stage, dma);
     return check_launch("viewshed_kernel");
 }
 
