@@ -184,6 +184,9 @@ struct FwdArgs {
     // score mode: tiles of BL x BL cells, one per workgroup, row-major
     int stride, BL;
     int64_t lat_r, lat_c, blocks_c;
+    // ceil(2^20 / BL) and ceil(2^20 / stride): x / BL = (x * bl_inv) >> 20
+    // exactly for x < BL^2 (BL <= 64), likewise for stride
+    uint32_t bl_inv, st_inv;
     float *score;
 };
 
@@ -408,11 +411,13 @@ cnn_fwd_kernel(FwdArgs A)
             wave_lds_sync();
         } else {
             const int wi = (int)w;  // < BL * BL
-            const int py = wi / A.BL, px = wi - py * A.BL;
-            const int64_t li = bi * A.BL + py, lj = bj * A.BL + px;
-            if (li >= A.lat_r || lj >= A.lat_c)
+            const int py = (int)(((uint32_t)wi * A.bl_inv) >> 20), px = wi - py * A.BL;
+            // cell lattice indices fit 31 bits (the lattice is at most the
+            // terrain, whose side is below 2^31)
+            const int li = (int)bi * A.BL + py, lj = (int)bj * A.BL + px;
+            if (li >= (int)A.lat_r || lj >= (int)A.lat_c)
                 continue;
-            pid = li * A.lat_c + lj;
+            pid = (int64_t)li * A.lat_c + lj;
             // highest post of the cell (elevation desc, index asc): one wave
             // max over packed (elevation, ~row-major position) keys
             const int ss = A.stride * A.stride;
@@ -421,7 +426,8 @@ cnn_fwd_kernel(FwdArgs A)
             if (ss <= 64) {
                 // one post per lane (row hr, column hc of the cell)
                 // rows and columns of the cell inside the terrain (uniform)
-                const int64_t rl64 = A.nrows - li * A.stride, cl64 = A.ncols - lj * A.stride;
+                const int64_t rl64 = A.nrows - (int64_t)li * A.stride;
+                const int64_t cl64 = A.ncols - (int64_t)lj * A.stride;
                 const int rl = rl64 < 64 ? (int)rl64 : 64, cl = cl64 < 64 ? (int)cl64 : 64;
                 const bool ok = lane < ss && hr < rl && hc < cl;
                 const int v = tile[cell0 + hoff];
@@ -429,7 +435,7 @@ cnn_fwd_kernel(FwdArgs A)
             } else {
                 for (int e = lane; e < ss; e += 64) {
                     const int r = e / A.stride, c = e - r * A.stride;
-                    if (li * A.stride + r < A.nrows && lj * A.stride + c < A.ncols) {
+                    if ((int64_t)li * A.stride + r < A.nrows && (int64_t)lj * A.stride + c < A.ncols) {
                         const int v = tile[cell0 + r * tp + c];
                         const int key = ((v + 32768) << 12) | (4095 - e);
                         best = key > best ? key : best;
@@ -440,9 +446,9 @@ cnn_fwd_kernel(FwdArgs A)
             // row moves shift in never win
             best = (int)wave_max_u32((uint32_t)(best < 0 ? 0 : best));
             const int e = 4095 - (best & 4095);
-            const int r = e / A.stride, c = e - r * A.stride;
-            cy = li * A.stride + r;
-            cx = lj * A.stride + c;
+            const int r = (int)(((uint32_t)e * A.st_inv) >> 20), c = e - r * A.stride;
+            cy = (int64_t)li * A.stride + r;
+            cx = (int64_t)lj * A.stride + c;
             or_ = py * A.stride + r;
             oc = px * A.stride + c;
         }
@@ -1104,6 +1110,8 @@ extern "C" int siting_cnn_score_terrain(const float *params, const int16_t *z, i
     // cells per tile side: BL * stride <= 64 posts plus the 63-post patch
     // margin (two workgroups per CU at every stride)
     a.BL = std::max(1, kScoreSpan / stride);
+    a.bl_inv = ((1u << 20) + (uint32_t)a.BL - 1) / (uint32_t)a.BL;
+    a.st_inv = ((1u << 20) + (uint32_t)stride - 1) / (uint32_t)stride;
     a.lat_r = (nrows + stride - 1) / stride;
     a.lat_c = (ncols + stride - 1) / stride;
     const int64_t blocks_r = (a.lat_r + a.BL - 1) / a.BL;
