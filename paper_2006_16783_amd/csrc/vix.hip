@@ -95,9 +95,20 @@ __device__ __forceinline__ int mad_i24(int a, int b, int c)
     return r;
 }
 
+// -1, 0 or 1 by the sign of a (one v_med3_i32; the compiler's form of the
+// clamp is two compares and two selects)
+__device__ __forceinline__ int sign3(int a)
+{
+    int r;
+    asm("v_med3_i32 %0, %1, -1, 1" : "=v"(r) : "v"(a));
+    return r;
+}
+
+// queue entry: dx and dy as 13-bit two's complement fields (bits 13..25 and
+// 0..12); kSkip, with its top bits set, is no entry
 __device__ __forceinline__ uint32_t pack_test(int dx, int dy)
 {
-    return ((uint32_t)(dx + 4096) << 13) | (uint32_t)(dy + 4096);
+    return ((uint32_t)(dx & 0x1FFF) << 13) | (uint32_t)(dy & 0x1FFF);
 }
 
 // LDS read at a byte address (the address includes the tile's base, so the
@@ -209,7 +220,6 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
     const int tile_cols = (int)((c0 + T > ncols ? ncols : c0 + T) - c0);
     const int R2 = R * R;
     const int nposts = T * T, nbatch = (nposts + 63) >> 6;
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
     auto claim = [&]() {
         int bt = 0;
@@ -244,11 +254,6 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
     // (row j of the wavefront's queue)
     uint32_t e[kVixChunk];
     int j0 = 0, kc = 0, cursor = 0, total = 0;
-    // row r of the queue (r wave-uniform; kSkip past the end)
-    auto e_row = [&](int r) {
-        const uint32_t v = e[r < kVixChunk ? r : kVixChunk - 1];  // indexed register read
-        return r < kVixChunk ? v : kSkip;
-    };
 
     auto setup = [&](int bt) {
         int py, px;
@@ -360,7 +365,7 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
         setup(bt_first);
         generate();
     }
-    bool active = false;
+    int act = 0;  // this lane runs a test (an int: the ballot below is one compare)
     // LOS state: n major steps, mn minor steps; e = r - n < 0 with r the
     // minor remainder, kept as an unsigned word so that e + mn >= 0 is the
     // carry of the add; off: the current post (its LDS byte address, or its
@@ -370,18 +375,27 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
     uint32_t eu = 0;
     // idle lanes take the next tests of the queue, in order
     auto take = [&]() {
-        const bool idle = !active;
-        const uint64_t m = __ballot(idle);
-        const int idx = cursor + __popcll(m & lt_mask);
+        const uint64_t m = __ballot(act == 0);
+        // queue position of this lane's test: cursor + idle lanes below it
+        const int idx = (int)__builtin_amdgcn_mbcnt_hi(
+            (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, (uint32_t)cursor));
         const int src = idx & 63;
+        // positions cursor .. cursor+63 hold every lane once: lane L's entry
+        // is in row cursor/64 when L >= cursor%64, else in the next row (row
+        // indexes wave-uniform; a next row past the chunk is clamped, its
+        // positions are >= total and never taken)
         const int row = cursor >> 6;
-        const uint32_t v0 = lane_read(src, e_row(row)), v1 = lane_read(src, e_row(row + 1));
+        const int row1 = row + 1 < kVixChunk ? row + 1 : kVixChunk - 1;
+        uint32_t v0 = e[row], v1 = e[row1];  // indexed register reads
+        // both rows in registers before the select (else the select moves
+        // into the index, which is then per lane and sends e[] to scratch)
+        asm volatile("" : "+v"(v0), "+v"(v1));
+        const uint32_t mine = lane >= (cursor & 63) ? v0 : v1;
+        const uint32_t ent = lane_read(src, mine);
         const int spo = (int)lane_read(src, (uint32_t)po);
         const int sE = (int)lane_read(src, (uint32_t)Epost);
-        const uint32_t ent = (idx >> 6) == (cursor >> 6) ? v0 : v1;
-        if (idle && idx < total && ent != kSkip) {
-            const int dx = (int)((ent >> 13) & 0x1FFF) - 4096;
-            const int dy = (int)(ent & 0x1FFF) - 4096;
+        if (act == 0 && idx < total && ent != kSkip) {
+            const int dx = (int)(ent << 6) >> 19, dy = (int)(ent << 19) >> 19;
             const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
             const bool xmaj = adx >= ady;
             const int cidx = (buf << 6) | src;
@@ -389,36 +403,40 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
             if (n <= 1) {
                 add_visible(cidx);  // adjacent: always visible
             } else {
-                const int sx = dx < 0 ? -1 : 1, sy = dy < 0 ? -rs : rs;
                 const int es = kLds ? 2 : 1;  // offset units per post
+                // unit steps along x and y (0 along an axis the line does not
+                // move on): the minor step is then 0 when the minor extent is
+                // 0, so the second post of a sample (minor offset q+1) is read
+                // at offset q, inside the observer-receiver box (its weight r
+                // is always 0)
+                const int ux = sign3(dx), uy = sign3(dy);
+                const int gx = ux * es;
+                // in LDS the row step (2 * pitch bytes) is below 2^23; a global
+                // row step (ld) may not be
+                const int gy = kLds ? mul_i24(uy, rs * 2) : (uy < 0 ? -rs : uy > 0 ? rs : 0);
                 mn = xmaj ? ady : adx;
-                smaj = (xmaj ? sx : sy) * es;
-                // the second post of a sample is read at minor offset q+1; with
-                // no minor extent its weight r is always 0 and q+1 would leave
-                // the observer-receiver box (past the terrain's last row or
-                // column), so it is read at offset q instead
-                smin = mn == 0 ? 0 : (xmaj ? sy : sx) * es;
-                const int tgt = spo + (kLds ? mul_i24(dy, rs) : dy * rs) + dx;
-                const int Zt = (int)zb[tgt] + h_r;
+                smaj = xmaj ? gx : gy;
+                smin = xmaj ? gy : gx;
+                off = kLds ? tb + spo * 2 : spo;
+                const int tgt = kLds ? mad_i24(dy, rs * 2, off) + dx * 2 : spo + dy * rs + dx;
+                const int Zt = kLds ? lds_read_i16(tgt) : (int)zb[tgt];
                 if (!kLds)
                     note(zb_off + tgt);
-                off = kLds ? tb + spo * 2 : spo;
                 rhs = mul_i24(sE, n);  // |sE| < 2^17, n < 2^14
-                dz = Zt - sE;
+                dz = Zt + (h_r - sE);
                 eu = (uint32_t)-n;
                 k = n - 1;  // steps left
                 pl = cidx;
-                active = true;
+                act = 1;
             }
         }
-        const int c1 = cursor + __popcll(m);
-        cursor = c1;
+        cursor += (int)__builtin_popcountll(m);
     };
 
     // kSPI steps of every active test: positions and reads first, then the
     // comparisons, so a test waits for memory once per block
     auto step_block = [&]() {
-        if (!active)
+        if (act == 0)
             return;
         int sa[kSPI], sb[kSPI], se[kSPI];
 #pragma unroll
@@ -435,7 +453,7 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
             } else {
                 sa[sp] = 0;
                 sb[sp] = 0;
-                if (sp < k) {
+                if (sp == 0 || sp < k) {
                     // both posts lie in the observer-receiver box: minor
                     // offsets q and q+1 <= |minor| (q+1 = q when |minor| = 0)
                     sa[sp] = zb[off];
@@ -452,7 +470,8 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
         for (int sp = 0; sp < kSPI; sp++) {
             rhs += dz;
             const int S = mad_i24(sb[sp] - sa[sp], se[sp], mul_i24(sb[sp], n));
-            const bool bs = sp < k && S > rhs;
+            // k >= 1 at every block start
+            const bool bs = (sp == 0 || sp < k) && S > rhs;
             blocked |= bs;
             if (kCount && bs && first == kSPI)
                 first = sp;
@@ -463,7 +482,7 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
         if (blocked || k <= 0) {
             if (!blocked)
                 add_visible(pl);
-            active = false;
+            act = 0;
         }
     };
 
@@ -483,7 +502,7 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
             const int nb = (buf + 1) & (kVixBufs - 1);
             bool can = true;
             if (pending & (1u << nb)) {
-                if (__any(active && (pl >> 6) == nb)) {
+                if (__any(act != 0 && (pl >> 6) == nb)) {
                     can = false;
                 } else {
                     retire(nb, (int)((bt_of >> (16 * nb)) & 0xFFFF));
@@ -509,7 +528,7 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
             generate();
             continue;
         }
-        if (!more && !__any(active))
+        if (!more && !__any(act != 0))
             break;
         // no new tests yet (or none left): advance the running ones
         step_block();
