@@ -59,9 +59,17 @@ constexpr int kSPI = 8;                // LOS steps per queue iteration
 constexpr int kVixBufs = 4;
 constexpr int kVixWaveLds = kVixBufs * 64;
 
+// a ^ b ^ k as one three-input bit operation (truth table 0x96); the
+// compiler emits two v_xor_b32 for the plain expression
+__device__ __forceinline__ uint32_t xor3_key(uint32_t a, uint32_t b, uint32_t k)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, k, 0x96);
+}
+
 // Philox4x32-10 block function (Salmon et al., SC'11): per round two 32x32
 // products (one v_mad_u64_u32 each), their high halves mixed with the other
-// counter words and the key, and the key bumped by the Weyl constants.
+// counter words and the key, and the key bumped by the Weyl constants.  The
+// key is wave-uniform (the seed).
 __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                               uint32_t k0, uint32_t k1, uint32_t out[4])
 {
@@ -70,8 +78,8 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
 #pragma unroll
     for (int round = 0; round < 10; round++) {
         const uint64_t p0 = (uint64_t)M0 * c0, p1 = (uint64_t)M1 * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3_key((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = xor3_key((uint32_t)(p0 >> 32), c3, k1);
         c0 = n0; c1 = (uint32_t)p1; c2 = n2; c3 = (uint32_t)p0;
         k0 += W0; k1 += W1;
     }
@@ -294,8 +302,9 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
             const uint32_t mx = __umul24(u & 0xFFFFu, wx), my = __umul24(u >> 16, wy);
             const int dx = bxo + (int)(mx >> 16);
             const int dy = byo + (int)(my >> 16);
-            const bool ok = (mx & 0xFFFFu) >= tx && (my & 0xFFFFu) >= ty &&
-                            (dx | dy) != 0 && __mul24(dx, dx) + __mul24(dy, dy) <= R2;
+            // every test evaluated (no branches around the later ones)
+            const bool ok = ((mx & 0xFFFFu) >= tx) & ((my & 0xFFFFu) >= ty) & ((dx | dy) != 0) &
+                            (__mul24(dx, dx) + __mul24(dy, dy) <= R2);
             const int att1 = att + 1;
             const bool acc = live && (ok || att1 == kVixMaxAttempts);
             att = acc ? 0 : (live ? att1 : att);
@@ -319,18 +328,22 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
                 propose(o[i], live);
             }
         }
-        // a new block per round for every lane that still needs draws
-        while (__any(made < need)) {
-            uint32_t o[4];
-            philox4x32_10((uint32_t)t, blk_next, (uint32_t)(t >> 32), 0, k0, k1, o);
-            const bool want = made < need;
-            blk_next += want ? 1 : 0;
+        // a new block per round for every lane that still needs draws (the
+        // exit test at the bottom: the queue then stays in its registers
+        // across rounds)
+        if (__any(made < need)) {
+            do {
+                uint32_t o[4];
+                philox4x32_10((uint32_t)t, blk_next, (uint32_t)(t >> 32), 0, k0, k1, o);
+                const bool want = made < need;
+                blk_next += want ? 1 : 0;
 #pragma unroll
-            for (int i = 0; i < 4; i++) {
-                const bool live = made < need;
-                nbuf = live ? 3 - i : nbuf;
-                propose(o[i], live);
-            }
+                for (int i = 0; i < 4; i++) {
+                    const bool live = made < need;
+                    nbuf = live ? 3 - i : nbuf;
+                    propose(o[i], live);
+                }
+            } while (__any(made < need));
         }
         // rows 0..kc-1 to e[0..kc-1]
         for (int s = kc; s < kVixChunk; s++) {
