@@ -306,9 +306,11 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
             const uint32_t mx = __umul24(u & 0xFFFFu, wx), my = __umul24(u >> 16, wy);
             const int dx = bxo + (int)(mx >> 16);
             const int dy = byo + (int)(my >> 16);
-            // every test evaluated (no branches around the later ones)
-            const bool ok = ((mx & 0xFFFFu) >= tx) & ((my & 0xFFFFu) >= ty) & ((dx | dy) != 0) &
-                            (__mul24(dx, dx) + __mul24(dy, dy) <= R2);
+            // every test evaluated (no branches around the later ones); the
+            // receiver is off the post and in the disk iff 0 < dx^2 + dy^2 <=
+            // R^2, i.e. dx^2 + dy^2 - 1 < R^2 as unsigned values (0 wraps)
+            const uint32_t d2m1 = (uint32_t)mad_i24(dy, dy, mad_i24(dx, dx, -1));
+            const bool ok = ((mx & 0xFFFFu) >= tx) & ((my & 0xFFFFu) >= ty) & (d2m1 < (uint32_t)R2);
             const int att1 = att + 1;
             const bool acc = live && (ok || att1 == kVixMaxAttempts);
             att = acc ? 0 : (live ? att1 : att);
