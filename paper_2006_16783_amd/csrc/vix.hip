@@ -51,7 +51,10 @@ constexpr int kVixThreads = 64 * kVixWaves;
 constexpr int kVixChunk = 10;          // draws per post per queue round
 constexpr int kVixMaxAttempts = 64;    // consecutive rejections before a draw fails
 constexpr int kVixMaxRoi = 4094;       // queue entries hold dx, dy in 13 bits
-constexpr uint32_t kSkip = 0xFFFFFFFFu;
+// queue words that hold no test: a slot not yet drawn, and a failed draw (or
+// a slot past the chunk); every test entry is below both
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+constexpr uint32_t kNoTest = 0xFFFFFFFEu;
 // LOS steps per queue iteration: longer blocks waste the steps after a
 // test's end (most tests end within a few steps), shorter ones take tests
 // more often; 5 measured fastest (and its narrower halo fits a 72-post tile
@@ -117,7 +120,7 @@ __device__ __forceinline__ int sign3(int a)
 }
 
 // queue entry: dx and dy as 13-bit two's complement fields (bits 13..25 and
-// 0..12); kSkip, with its top bits set, is no entry
+// 0..12); kEmpty and kNoTest, with their top bits set, are no entries
 __device__ __forceinline__ uint32_t pack_test(int dx, int dy)
 {
     return ((uint32_t)(dx & 0x1FFF) << 13) | (uint32_t)(dy & 0x1FFF);
@@ -293,16 +296,25 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
     auto generate = [&]() {
         kc = K - j0 < kVixChunk ? K - j0 : kVixChunk;
         const int need = valid ? kc : 0;
+        // the queue starts as need empty slots followed by no-test words;
+        // every draw (accepted or failed) enters at the end and shifts the
+        // queue towards e[0], so the lane still needs draws exactly while
+        // e[0] is empty, and after need draws they fill e[kVixChunk-need..]
 #pragma unroll
         for (int j = 0; j < kVixChunk; j++)
-            e[j] = kSkip;
-        int made = 0, att = 0;
+            e[j] = j < need ? kEmpty : kNoTest;
+        // proposals are numbered by slot (wave-uniform: the words left by the
+        // previous chunk in slots 0..3, new blocks from slot 4); a lane's
+        // live slots run without a gap from its first until its chunk is
+        // full, so before slot sl it has rejected sl - s_next proposals in a
+        // row, s_next being the slot after its last draw
+        int s_next = 4 - nbuf;
         const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
         // one proposal: 16-bit halves scaled to the box with Lemire's
         // rejection, then the disk test; an accepted draw (or a failed one
         // after kVixMaxAttempts rejections) is appended to the lane's queue.
         // Branch-free, so that the queue shifts in place.
-        auto propose = [&](uint32_t u, bool live) {
+        auto propose = [&](uint32_t u, bool live, int sl) {
             const uint32_t mx = __umul24(u & 0xFFFFu, wx), my = __umul24(u >> 16, wy);
             const int dx = bxo + (int)(mx >> 16);
             const int dy = byo + (int)(my >> 16);
@@ -311,45 +323,46 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
             // R^2, i.e. dx^2 + dy^2 - 1 < R^2 as unsigned values (0 wraps)
             const uint32_t d2m1 = (uint32_t)mad_i24(dy, dy, mad_i24(dx, dx, -1));
             const bool ok = ((mx & 0xFFFFu) >= tx) & ((my & 0xFFFFu) >= ty) & (d2m1 < (uint32_t)R2);
-            const int att1 = att + 1;
-            const bool acc = live && (ok || att1 == kVixMaxAttempts);
-            att = acc ? 0 : (live ? att1 : att);
+            const bool fail = s_next == sl - (kVixMaxAttempts - 1);
+            const bool acc = live && (ok || fail);
+            s_next = acc ? sl + 1 : s_next;
 #pragma unroll
             for (int j = 0; j + 1 < kVixChunk; j++)
                 e[j] = acc ? e[j + 1] : e[j];
-            e[kVixChunk - 1] = acc ? (ok ? pack_test(dx, dy) : kSkip) : e[kVixChunk - 1];
-            made += acc ? 1 : 0;
+            e[kVixChunk - 1] = acc ? (ok ? pack_test(dx, dy) : kNoTest) : e[kVixChunk - 1];
             if (kCount && acc && ok)
                 tests++;
         };
         // words left in block blk_next-1 by the previous chunk of the post
-        if (__any(made < need && nbuf > 0)) {
+        if (__any(e[0] == kEmpty && nbuf > 0)) {
             uint32_t o[4];
             philox4x32_10((uint32_t)t, blk_next - 1, (uint32_t)(t >> 32), 0, k0, k1, o);
             const int nb0 = nbuf;
 #pragma unroll
             for (int i = 0; i < 4; i++) {
-                const bool live = made < need && i >= 4 - nb0;
+                const bool live = e[0] == kEmpty && i >= 4 - nb0;
                 nbuf = live ? 3 - i : nbuf;
-                propose(o[i], live);
+                propose(o[i], live, i);
             }
         }
         // a new block per round for every lane that still needs draws (the
         // exit test at the bottom: the queue then stays in its registers
         // across rounds)
-        if (__any(made < need)) {
+        if (__any(e[0] == kEmpty)) {
+            int sl = 4;  // slot of the round's first word
             do {
                 uint32_t o[4];
                 philox4x32_10((uint32_t)t, blk_next, (uint32_t)(t >> 32), 0, k0, k1, o);
-                const bool want = made < need;
+                const bool want = e[0] == kEmpty;
                 blk_next += want ? 1 : 0;
 #pragma unroll
                 for (int i = 0; i < 4; i++) {
-                    const bool live = made < need;
+                    const bool live = e[0] == kEmpty;
                     nbuf = live ? 3 - i : nbuf;
-                    propose(o[i], live);
+                    propose(o[i], live, sl + i);
                 }
-            } while (__any(made < need));
+                sl += 4;
+            } while (__any(e[0] == kEmpty));
         }
         // rows 0..kc-1 to e[0..kc-1]
         for (int s = kc; s < kVixChunk; s++) {
@@ -413,7 +426,7 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
         const uint32_t ent = lane_read(src, mine);
         const int spo = (int)lane_read(src, (uint32_t)po);
         const int sE = (int)lane_read(src, (uint32_t)Epost);
-        if (act == 0 && idx < total && ent != kSkip) {
+        if (act == 0 && idx < total && ent < kNoTest) {
             const int dx = (int)(ent << 6) >> 19, dy = (int)(ent << 19) >> 19;
             const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
             const bool xmaj = adx >= ady;
