@@ -428,7 +428,10 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
         const int sE = (int)lane_read(src, (uint32_t)Epost);
         if (act == 0 && idx < total && ent < kNoTest) {
             const int dx = (int)(ent << 6) >> 19, dy = (int)(ent << 19) >> 19;
-            const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
+            // unit steps along x and y (0 along an axis the line does not
+            // move on) and the extents |d| = d * sign(d)
+            const int ux = sign3(dx), uy = sign3(dy);
+            const int adx = mul_i24(dx, ux), ady = mul_i24(dy, uy);
             const bool xmaj = adx >= ady;
             const int cidx = (buf << 6) | src;
             n = xmaj ? adx : ady;
@@ -436,12 +439,10 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
                 add_visible(cidx);  // adjacent: always visible
             } else {
                 const int es = kLds ? 2 : 1;  // offset units per post
-                // unit steps along x and y (0 along an axis the line does not
-                // move on): the minor step is then 0 when the minor extent is
-                // 0, so the second post of a sample (minor offset q+1) is read
-                // at offset q, inside the observer-receiver box (its weight r
-                // is always 0)
-                const int ux = sign3(dx), uy = sign3(dy);
+                // with a unit step of 0 along an axis the line does not move
+                // on, the minor step is 0 when the minor extent is 0, so the
+                // second post of a sample (minor offset q+1) is read at offset
+                // q, inside the observer-receiver box (its weight r is always 0)
                 const int gx = ux * es;
                 // in LDS the row step (2 * pitch bytes) is below 2^23; a global
                 // row step (ld) may not be
