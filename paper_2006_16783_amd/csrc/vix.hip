@@ -50,11 +50,12 @@ constexpr int kVixWaves = 16;
 constexpr int kVixThreads = 64 * kVixWaves;
 constexpr int kVixChunk = 10;          // draws per post per queue round
 constexpr int kVixMaxAttempts = 64;    // consecutive rejections before a draw fails
-constexpr int kVixMaxRoi = 4094;       // queue entries hold dx, dy in 13 bits
+constexpr int kVixMaxRoi = 4094;       // LOS lengths keep every product in int32
 // queue words that hold no test: a slot not yet drawn, and a failed draw (or
-// a slot past the chunk); every test entry is below both
-constexpr uint32_t kEmpty = 0xFFFFFFFFu;
-constexpr uint32_t kNoTest = 0xFFFFFFFEu;
+// a slot past the chunk).  Their dx (32767) is no receiver's, and as signed
+// words every test entry is below both.
+constexpr uint32_t kEmpty = 0x7FFF7FFFu;
+constexpr uint32_t kNoTest = 0x7FFF7FFEu;
 // LOS steps per queue iteration: longer blocks waste the steps after a
 // test's end (most tests end within a few steps), shorter ones take tests
 // more often; 5 measured fastest (and its narrower halo fits a 72-post tile
@@ -110,6 +111,21 @@ __device__ __forceinline__ int mad_i24(int a, int b, int c)
     return r;
 }
 
+// the same with a wave-uniform second factor, read from a scalar register
+__device__ __forceinline__ int mul_i24_s(int a, int b)
+{
+    int r;
+    asm("v_mul_i32_i24 %0, %1, %2" : "=v"(r) : "v"(a), "s"(b));
+    return r;
+}
+
+__device__ __forceinline__ int mad_i24_s(int a, int b, int c)
+{
+    int r;
+    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
+    return r;
+}
+
 // -1, 0 or 1 by the sign of a (one v_med3_i32; the compiler's form of the
 // clamp is two compares and two selects)
 __device__ __forceinline__ int sign3(int a)
@@ -119,11 +135,11 @@ __device__ __forceinline__ int sign3(int a)
     return r;
 }
 
-// queue entry: dx and dy as 13-bit two's complement fields (bits 13..25 and
-// 0..12); kEmpty and kNoTest, with their top bits set, are no entries
+// queue entry: dx and dy as the high and low 16-bit halves (two's
+// complement), one byte permute
 __device__ __forceinline__ uint32_t pack_test(int dx, int dy)
 {
-    return ((uint32_t)(dx & 0x1FFF) << 13) | (uint32_t)(dy & 0x1FFF);
+    return __builtin_amdgcn_perm((uint32_t)dx, (uint32_t)dy, 0x05040100u);
 }
 
 // LDS read at a byte address (the address includes the tile's base, so the
@@ -341,7 +357,8 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
 #pragma unroll
             for (int i = 0; i < 4; i++) {
                 const bool live = e[0] == kEmpty && i >= 4 - nb0;
-                nbuf = live ? 3 - i : nbuf;
+                if (K > kVixChunk)  // words left matter only to a later chunk
+                    nbuf = live ? 3 - i : nbuf;
                 propose(o[i], live, i);
             }
         }
@@ -358,7 +375,8 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
 #pragma unroll
                 for (int i = 0; i < 4; i++) {
                     const bool live = e[0] == kEmpty;
-                    nbuf = live ? 3 - i : nbuf;
+                    if (K > kVixChunk)
+                        nbuf = live ? 3 - i : nbuf;
                     propose(o[i], live, sl + i);
                 }
                 sl += 4;
@@ -426,8 +444,8 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
         const uint32_t ent = lane_read(src, mine);
         const int spo = (int)lane_read(src, (uint32_t)po);
         const int sE = (int)lane_read(src, (uint32_t)Epost);
-        if (act == 0 && idx < total && ent < kNoTest) {
-            const int dx = (int)(ent << 6) >> 19, dy = (int)(ent << 19) >> 19;
+        if (act == 0 && idx < total && (int)ent < (int)kNoTest) {
+            const int dx = (int)ent >> 16, dy = (int)(ent << 16) >> 16;
             // unit steps along x and y (0 along an axis the line does not
             // move on) and the extents |d| = d * sign(d)
             const int ux = sign3(dx), uy = sign3(dy);
@@ -446,12 +464,12 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
                 const int gx = ux * es;
                 // in LDS the row step (2 * pitch bytes) is below 2^23; a global
                 // row step (ld) may not be
-                const int gy = kLds ? mul_i24(uy, rs * 2) : (uy < 0 ? -rs : uy > 0 ? rs : 0);
+                const int gy = kLds ? mul_i24_s(uy, rs * 2) : (uy < 0 ? -rs : uy > 0 ? rs : 0);
                 mn = xmaj ? ady : adx;
                 smaj = xmaj ? gx : gy;
                 smin = xmaj ? gy : gx;
                 off = kLds ? tb + spo * 2 : spo;
-                const int tgt = kLds ? mad_i24(dy, rs * 2, off) + dx * 2 : spo + dy * rs + dx;
+                const int tgt = kLds ? mad_i24_s(dy, rs * 2, off) + dx * 2 : spo + dy * rs + dx;
                 const int Zt = kLds ? lds_read_i16(tgt) : (int)zb[tgt];
                 if (!kLds)
                     note(zb_off + tgt);
