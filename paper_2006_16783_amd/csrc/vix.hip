@@ -282,8 +282,10 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
     uint32_t pending = 0;
     uint64_t bt_of = 0;
     // queue of the current chunk: e[j] holds draw j0+j of this lane's post
-    // (row j of the wavefront's queue)
-    uint32_t e[kVixChunk];
+    // (row j of the wavefront's queue); e[kVixChunk] always holds a no-test
+    // word, so that the rows a take may read past the chunk hold no tests
+    uint32_t e[kVixChunk + 1];
+    e[kVixChunk] = kNoTest;
     int j0 = 0, kc = 0, cursor = 0, total = 0;
 
     auto setup = [&](int bt) {
@@ -382,10 +384,10 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
                 sl += 4;
             } while (__any(e[0] == kEmpty));
         }
-        // rows 0..kc-1 to e[0..kc-1]
+        // rows 0..kc-1 to e[0..kc-1], no-test words shifted in behind them
         for (int s = kc; s < kVixChunk; s++) {
 #pragma unroll
-            for (int j = 0; j + 1 < kVixChunk; j++)
+            for (int j = 0; j < kVixChunk; j++)
                 e[j] = e[j + 1];
         }
         cursor = 0;
@@ -432,10 +434,9 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
         const int src = idx & 63;
         // positions cursor .. cursor+63 hold every lane once: lane L's entry
         // is in row cursor/64 when L >= cursor%64, else in the next row (row
-        // indexes wave-uniform; a next row past the chunk is clamped, its
-        // positions are >= total and never taken)
+        // indexes wave-uniform; positions from total on hold no tests)
         const int row = cursor >> 6;
-        const int row1 = row + 1 < kVixChunk ? row + 1 : kVixChunk - 1;
+        const int row1 = row + 1;
         uint32_t v0 = e[row], v1 = e[row1];  // indexed register reads
         // both rows in registers before the select (else the select moves
         // into the index, which is then per lane and sends e[] to scratch)
@@ -444,7 +445,7 @@ __global__ __launch_bounds__(kVixThreads) void vix_kernel(
         const uint32_t ent = lane_read(src, mine);
         const int spo = (int)lane_read(src, (uint32_t)po);
         const int sE = (int)lane_read(src, (uint32_t)Epost);
-        if (act == 0 && idx < total && (int)ent < (int)kNoTest) {
+        if (act == 0 && (int)ent < (int)kNoTest) {
             const int dx = (int)ent >> 16, dy = (int)(ent << 16) >> 16;
             // unit steps along x and y (0 along an axis the line does not
             // move on) and the extents |d| = d * sign(d)
