@@ -58,10 +58,14 @@ def log(*a):
 
 
 def source_hash(names):
+    """Sources and compile flags of a kernel (counter records match on it)."""
+    from paper_2006_16783_amd import build as B
     h = hashlib.sha256()
     for n in names:
         with open(os.path.join(ROOT, "paper_2006_16783_amd", "csrc", n), "rb") as f:
             h.update(f.read())
+        if n.endswith(".hip"):
+            h.update(" ".join(B.flags_of(n)).encode())
     return h.hexdigest()[:16]
 
 

@@ -22,6 +22,20 @@ HIPCC_FLAGS = [
 ]
 
 
+# Extra device-pass flags per source.  VIX (issue-bound integer work with
+# LDS reads in blocks) is scheduled for instruction-level parallelism: at
+# 46400^2, ROI 100 the kernel took 176.0 ms against 176.7 ms with the default
+# scheduler, with identical counts.
+FILE_FLAGS = {
+    "vix.hip": ["-Xarch_device", "-mllvm=-misched=gcn-max-ilp"],
+}
+
+
+def flags_of(name: str):
+    """Every compile flag a source is built with (also keys profile records)."""
+    return [*HIPCC_FLAGS, *FILE_FLAGS.get(name, [])]
+
+
 def hipcc() -> str:
     for c in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
         if c and os.path.exists(c):
@@ -34,19 +48,42 @@ def sources():
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every HIP source into paper_2006_16783_amd/libsiting.so."""
+    """Compile every HIP source (in parallel, each with its own flags) and link
+    them into paper_2006_16783_amd/libsiting.so."""
+    import tempfile
     srcs = sources()
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(HERE, "..", "include"),
-           "-Wl,--version-script=" + os.path.join(CSRC, "exports.map"), "-o", tmp, *srcs]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building libsiting.so")
-    if verbose and r.stderr.strip():
-        sys.stderr.write(r.stderr)
+    inc = ["-I", os.path.join(HERE, "..", "include")]
+    with tempfile.TemporaryDirectory(prefix="siting_build_") as tmpd:
+        procs, objs = [], []
+        for src in srcs:
+            name = os.path.basename(src)
+            obj = os.path.join(tmpd, name + ".o")
+            cflags = [f for f in flags_of(name) if f != "-shared"]
+            cmd = [hipcc(), *cflags, *inc, "-c", "-o", obj, src]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            procs.append((name, subprocess.Popen(cmd, stdout=subprocess.PIPE,
+                                                 stderr=subprocess.STDOUT, text=True)))
+            objs.append(obj)
+        failed = False
+        for name, pr in procs:
+            out, _ = pr.communicate()
+            if pr.returncode != 0:
+                failed = True
+                sys.stderr.write(out)
+            elif verbose and out.strip():
+                sys.stderr.write(out)
+        if failed:
+            raise RuntimeError("hipcc failed building libsiting.so")
+        tmp = LIB + ".tmp%d" % os.getpid()
+        cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}",
+               "-Wl,--version-script=" + os.path.join(CSRC, "exports.map"), "-o", tmp, *objs]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError("hipcc failed linking libsiting.so")
     os.replace(tmp, LIB)
     return LIB
 
