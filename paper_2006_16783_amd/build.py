@@ -22,12 +22,15 @@ HIPCC_FLAGS = [
 ]
 
 
-# Extra device-pass flags per source.  VIX (issue-bound integer work with
-# LDS reads in blocks) is scheduled for instruction-level parallelism: at
-# 46400^2, ROI 100 the kernel took 176.0 ms against 176.7 ms with the default
-# scheduler, with identical counts.
+# Extra device-pass flags per source, measured at 46400^2, ROI 100 with
+# identical results.  VIX (issue-bound integer work with LDS reads in blocks)
+# and SITE (one wavefront, latency-bound) are scheduled for instruction-level
+# parallelism: VIX 176.0 ms against 176.7 ms with the default scheduler, SITE
+# 16.7 ms against 17.6 ms.  VIEWSHED gained nothing from it (5.88 / 5.90 ms).
+_ILP = ["-Xarch_device", "-mllvm=-misched=gcn-max-ilp"]
 FILE_FLAGS = {
-    "vix.hip": ["-Xarch_device", "-mllvm=-misched=gcn-max-ilp"],
+    "vix.hip": _ILP,
+    "greedy.hip": _ILP,
 }
 
 
