@@ -25,6 +25,25 @@ def test_every_declared_symbol_is_exported_and_bound():
     assert S.siting_abi_version() == 1
 
 
+def test_every_source_keeps_the_mandatory_device_flags():
+    """Per-source scheduler flags only add to the common ones: every HIP source
+    is built for gfx950 at -O3 without packed-FP32 instructions, and extra
+    LLVM options reach the device pass only."""
+    from paper_2006_16783_amd import build as B
+    srcs = [os.path.basename(p) for p in B.sources()]
+    assert "vix.hip" in srcs and set(B.FILE_FLAGS) <= set(srcs)
+    for name in srcs:
+        f = B.flags_of(name)
+        assert f[:len(B.HIPCC_FLAGS)] == B.HIPCC_FLAGS
+        i = f.index("-packed-fp32-ops")
+        assert f[i - 3:i] == ["-Xclang", "-target-feature", "-Xclang"]
+        assert "-O3" in f and any(x.startswith("--offload-arch=gfx950") for x in f)
+        extra = f[len(B.HIPCC_FLAGS):]
+        for j, x in enumerate(extra):
+            if x.startswith("-mllvm="):
+                assert j > 0 and extra[j - 1] == "-Xarch_device", (name, extra)
+
+
 def test_validation_errors_before_launch():
     lib = L.lib()
     assert lib.siting_vix(None, 10, 10, 10, 5, 1, 1, 4, 0, None, None) == -1
