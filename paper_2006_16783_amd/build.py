@@ -22,11 +22,14 @@ HIPCC_FLAGS = [
 ]
 
 
-# Extra device-pass flags per source, measured at 46400^2, ROI 100 with
-# identical results.  VIX (issue-bound integer work with LDS reads in blocks)
-# and SITE (one wavefront, latency-bound) are scheduled for instruction-level
-# parallelism: VIX 176.0 ms against 176.7 ms with the default scheduler, SITE
-# 16.7 ms against 17.6 ms.  VIEWSHED gained nothing from it (5.88 / 5.90 ms).
+# Extra device-pass flags per source, measured with identical results.  The
+# LDS-tile VIX kernels (vix.hip; issue-bound integer work with LDS reads in
+# blocks) and SITE (one wavefront, latency-bound) are scheduled for
+# instruction-level parallelism: at 46400^2, ROI 100, VIX 176.0 ms against
+# 176.7 ms with the default scheduler, SITE 16.7 ms against 17.6 ms.  The
+# global-read VIX kernels (vix_global.hip, large ROI) keep the default: with
+# it 3.23 s against 3.43 s at 16384^2, ROI 500.  VIEWSHED gained nothing from
+# it (5.88 / 5.90 ms).
 _ILP = ["-Xarch_device", "-mllvm=-misched=gcn-max-ilp"]
 FILE_FLAGS = {
     "vix.hip": _ILP,

@@ -624,8 +624,18 @@ __global__ void vix_stats_finish(unsigned long long *stats)
 }
 
 }  // namespace
+
+// Launches the global-read instantiations (large ROI).  They live in a
+// translation unit of their own (vix_global.hip) so that they can be compiled
+// with another instruction scheduler than the LDS ones here.
+void vix_launch_global(bool with_stats, unsigned grid, size_t lds, hipStream_t s,
+                       const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld, int R,
+                       int h_t, int h_r, int K, uint64_t seed, uint8_t *count, int T,
+                       int64_t tiles_r, int64_t tiles_c, int64_t per_xcd, int tile_bytes, int dma,
+                       unsigned long long *stats);
 }  // namespace siting
 
+#ifndef SITING_VIX_GLOBAL_TU
 using namespace siting;
 
 static int vix_launch(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld, int32_t roi,
@@ -697,10 +707,10 @@ static int vix_launch(const int16_t *z, int64_t nrows, int64_t ncols, int64_t ld
         VIX_LAUNCH(true, true);
     else if (use_lds)
         VIX_LAUNCH(true, false);
-    else if (stats)
-        VIX_LAUNCH(false, true);
     else
-        VIX_LAUNCH(false, false);
+        vix_launch_global(stats != nullptr, (unsigned)grid, lds, s, z, nrows, ncols, ld, roi, h_t,
+                          h_r, K, seed, count, T, tiles_r, tiles_c, per_xcd, tile_bytes, dma,
+                          stats);
 #undef VIX_LAUNCH
     int rc = check_launch("vix_kernel");
     if (rc == SITING_OK && stats) {
@@ -728,3 +738,4 @@ extern "C" int siting_vix_stats(const int16_t *z, int64_t nrows, int64_t ncols, 
     return vix_launch(z, nrows, ncols, ld, roi, h_t, h_r, K, seed, count,
                       reinterpret_cast<unsigned long long *>(stats), stream, "siting_vix_stats");
 }
+#endif  // SITING_VIX_GLOBAL_TU
